@@ -1,0 +1,84 @@
+"""Planted mistakes: each edit below is a plausible slip in the oracle (a
+dropped term, a wrong sign, index or constant).  A copy of the oracle with the
+edit is compiled on the CPU and the pins are run against it; at least one pin
+must fail, otherwise the pins would not have caught that mistake."""
+import math
+
+import pytest
+
+import oracle
+from tests import test_oracle_end_to_end as E2E
+from tests import test_oracle_pins as PINS
+
+MUTANTS = {
+    "kepler_step_sign": ("E -= step;", "E += step;"),
+    "kepler_denominator": ("(1.0 - e * cos(E))", "(1.0 + e * cos(E))"),
+    "mean_anomaly_alg1_garble": ("Omega * time_s + t->alpha_rad", "Omega * (time_s + t->alpha_rad)"),
+    "sqrt_one_minus_e2": ("sqrt(1.0 - e * e) * sin(E)", "sqrt(1.0 + e * e) * sin(E)"),
+    "sin_cos_psi_swapped": ("* sin(t->omega_rad)\n", "* cos(t->omega_rad)\n"),
+    "no_zero_offset": ("double d0 = tbo_roemer_delay(t, 0.0);", "double d0 = 0.0;"),
+    "index_sign": ("src[j] = j - (int64_t)rint(dj);", "src[j] = j + (int64_t)rint(dj);"),
+    "index_floor": ("src[j] = j - (int64_t)rint(dj);", "src[j] = j - (int64_t)floor(dj);"),
+    "oob_clamps": ("(double)x0[s] : 0.0;", "(double)x0[s] : (double)x0[s < 0 ? 0 : n - 1];"),
+    "mean_divisor": ("double mean = sum / (double)n;", "double mean = sum / (double)(n - 1);"),
+    "dft_sign": ("ai -= y[j] * s[r];", "ai += y[j] * s[r];"),
+    "fft_twiddle_sign": ("double wr = c[q * step], wi = -s[q * step];", "double wr = c[q * step], wi = s[q * step];"),
+    "fft_twiddle_index": ("double wr = c[q * step], wi = -s[q * step];", "double wr = c[q], wi = -s[q];"),
+    "power_drops_imag": ("p[k] = re[k] * re[k] + im[k] * im[k];", "p[k] = re[k] * re[k];"),
+    "median_rank": ("meds[b] = tmp[(cnt - 1) / 2];", "meds[b] = tmp[cnt / 2];"),
+    "block_centre": ("cent[b] = (double)start + (double)(cnt - 1) / 2.0;", "cent[b] = (double)start + (double)cnt / 2.0;"),
+    "whiten_ln2": ("p[k] * M_LN2 / level", "p[k] / level"),
+    "whiten_no_interp": ("level = meds[b] + (meds[b + 1] - meds[b]) * f;", "level = meds[b];"),
+    "harmsum_rounding": ("acc += phat[(2 * mm * k + 2 * h) / (4 * h)];", "acc += phat[(2 * mm * k) / (4 * h)];"),
+    "harmsum_even_terms": ("for (int64_t mm = 1; mm < h2; mm += 2)", "for (int64_t mm = 1; mm < h2; mm += 1)"),
+    "tail_missing_term": ("for (int32_t k = 0; k < h; ++k) acc +=", "for (int32_t k = 0; k + 1 < h; ++k) acc +="),
+    "gauss_tail_two_sided": ("return log(0.5 * erfc(z / sqrt(2.0)));", "return log(erfc(z / sqrt(2.0)));"),
+    "fmin_not_scaled_by_fold": ("int64_t klo = h * J->kmin;", "int64_t klo = J->kmin;"),
+    "fold_pick_index": ("for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * hp)];",
+                        "for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * h)];"),
+}
+
+
+def _pins():
+    """Every pin as a zero-argument callable."""
+    out = []
+    for e in [0.02, 0.1]:
+        out.append(lambda e=e: PINS.test_kepler_matches_appendix_b_series(None, e))
+    for e in [0.1, 0.5]:
+        out.append(lambda e=e: PINS.test_kepler_against_high_precision(None, e))
+    for tm in PINS.TEMPLATES:
+        out.append(lambda tm=tm: PINS.test_resample_index_hand_values(None, tm))
+    for f in [PINS.test_zero_orbit_is_identity, PINS.test_circular_equals_elliptical_limit_and_phase_flip,
+              PINS.test_out_of_range_reads_zero, PINS.test_mean_subtract, PINS.test_naive_dft_brute_force_2_10,
+              PINS.test_parseval_and_pure_tone, PINS.test_whiten_constant_spectrum,
+              PINS.test_whiten_linear_ramp_odd_window, PINS.test_whiten_medians_brute_force,
+              PINS.test_harmsum_comb_closed_form, PINS.test_harmsum_direct_brute_force, PINS.test_thresholds,
+              PINS.test_sigma_conversion, E2E.test_search_output_sorted_and_consistent,
+              E2E.test_injected_binary_peaks_at_true_template_and_frequency]:
+        out.append(lambda f=f: f(None))
+    out.append(lambda: PINS.test_fft_against_library(None, 14))
+    return out
+
+
+def _caught(path):
+    with oracle.use_library(path):
+        for pin in _pins():
+            try:
+                pin()
+            except (AssertionError, ValueError, ZeroDivisionError, OverflowError):
+                return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(oracle_lib, name, tmp_path):
+    old, new = MUTANTS[name]
+    src = oracle.source_text()
+    assert src.count(old) >= 1, "mutation site vanished: " + name
+    path = oracle.build_variant(src.replace(old, new), str(tmp_path))
+    assert _caught(path), "no pin caught: " + name
+
+
+def test_unmodified_oracle_passes_every_pin(oracle_lib, tmp_path):
+    path = oracle.build_variant(oracle.source_text(), str(tmp_path))
+    assert not _caught(path)
