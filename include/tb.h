@@ -1,0 +1,182 @@
+/*
+ * tb.h -- C ABI of the MI355X (gfx950) template-bank coherent orbital search.
+ *
+ * The library implements the per-template search of Balakrishnan et al.,
+ * "Coherent Search for Binary Pulsars across all Five Keplerian Parameters in
+ * Radio Observations using the template-bank algorithm" (arXiv:2112.11991):
+ * for every Keplerian orbital template it removes the Roemer delay from a
+ * dedispersed time series by nearest-sample resampling (App. A.1, Algorithm
+ * 1), takes a real-to-complex FFT (the spin-frequency grid of Sec. 2.4), forms
+ * and whitens the power spectrum ("Fourier de-reddening", Sec. 5.2), sums up
+ * to 16 harmonics (Sec. 2.1) and keeps every bin above a false-alarm
+ * threshold (Sec. 2.1).  All of it runs in hand-written HIP kernels.
+ *
+ * Conventions
+ *  - Every call returns a tb_status; errors are negative.  Nothing is thrown
+ *    across the ABI.  tb_strerror() names a status.
+ *  - Host buffers passed in are owned by the caller and only read or written
+ *    during the call.  Device pointers (TB_MEM_DEVICE) must stay valid until
+ *    the call returns.  Everything the plan allocates it owns and frees in
+ *    tb_destroy().
+ *  - One plan may be used from several host threads; calls are serialised by
+ *    a mutex inside the plan.
+ *  - Series length n must be a power of two in [2^10, 2^max_log2n],
+ *    max_log2n <= 24.
+ */
+#ifndef TB_H
+#define TB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tb_plan_s* tb_plan_t;
+
+typedef enum {
+    TB_OK = 0,
+    TB_ERR_INVALID_ARG = -1, /* bad argument: NULL, non-power-of-two n, e >= 1, tau < 0, ... */
+    TB_ERR_OOM = -2,         /* device or host allocation failed */
+    TB_ERR_BUDGET = -3,      /* the plan's HBM budget would be exceeded */
+    TB_ERR_DEVICE = -4,      /* a HIP runtime call failed */
+    TB_ERR_OVERFLOW = -5,    /* more candidates than the request's ring holds; the
+                                count is still exact and the first ring_capacity
+                                records found are returned */
+    TB_ERR_NOT_READY = -6,   /* tb_poll / non-blocking tb_get_candidates: still running */
+    TB_ERR_UNKNOWN_ID = -7   /* no such series or request */
+} tb_status;
+
+enum { TB_MEM_HOST = 0, TB_MEM_DEVICE = 1 };
+
+typedef struct {
+    uint32_t max_log2n;        /* largest series accepted, log2 samples, 10..24 */
+    uint32_t harm_max;         /* harmonics summed: 1, 2, 4, 8 or 16 (Sec. 2.1; 16 in Sec. 5.2) */
+    uint32_t whiten_window;    /* W, spectral bins per median block of the whitening, 1..8192 */
+    uint32_t batch_templates;  /* templates in flight per launch; 0 = chosen by the plan */
+    double threshold_sigma;    /* one-sided Gaussian-equivalent false-alarm threshold (Sec. 2.1) */
+    double fmin_hz;            /* lowest fundamental searched (default 1 Hz) */
+    double fmax_hz;            /* highest fundamental searched; 0 = Nyquist */
+    uint64_t hbm_budget_bytes; /* device memory the plan may hold; 0 = no limit */
+    uint64_t ring_capacity;    /* candidate records kept per request (default 1<<20) */
+    void* stream;              /* hipStream_t the plan launches on; NULL = a stream of its own */
+    int32_t device;            /* HIP device ordinal; the plan makes it current on each call */
+    uint32_t flags;            /* reserved, 0 */
+} tb_config;
+
+/* One Keplerian orbital template (Sec. 2.1): P_orb = 2 pi / Omega, tau = a sin(eps)/c,
+ * alpha the initial orbital phase (M = Omega t + alpha), e the eccentricity,
+ * omega (psi in the paper) the longitude of periastron.  Circular: ecc = omega_rad = 0. */
+typedef struct {
+    double porb_s;
+    double tau_lts;
+    double alpha_rad;
+    double ecc;
+    double omega_rad;
+} tb_template;
+
+/* One bin of a harmonic fold above threshold (App. A "peak detection"). */
+typedef struct {
+    uint32_t series_id;
+    uint32_t template_id;  /* first_template_id + index within the request */
+    uint32_t bin;          /* k: the h-th harmonic bin, fundamental at k/h bins */
+    uint8_t log2_harm;     /* h = 2^log2_harm harmonics summed */
+    uint8_t reserved[3];
+    float power;           /* S_h[k], sum of h whitened powers */
+    float sigma;           /* Gaussian-equivalent significance of S_h[k] (Sec. 2.1) */
+    double freq_hz;        /* fundamental frequency k / (h T), T = n tsamp */
+} tb_candidate;
+
+/* Fills cfg with the defaults: max_log2n 24, harm_max 16, whiten_window 4096,
+ * threshold_sigma 6, fmin_hz 1, fmax_hz 0, no budget, ring 1<<20, own stream,
+ * device 0. */
+void tb_default_config(tb_config* cfg);
+
+/* Creates a plan: checks cfg, makes device cfg->device current, creates or
+ * adopts the stream.  Returns TB_ERR_INVALID_ARG for a bad cfg, TB_ERR_DEVICE
+ * if the device cannot be used. */
+tb_status tb_plan(const tb_config* cfg, tb_plan_t* out);
+
+/* Waits for the plan's work, frees everything it owns.  NULL is a no-op. */
+tb_status tb_destroy(tb_plan_t plan);
+
+/* Copies a dedispersed series S_i, i = 0..n-1 at times i*tsamp (App. A.1),
+ * into plan memory (from host, or device-to-device on the plan stream for
+ * TB_MEM_DEVICE) and removes its mean in double precision.  Returns the new
+ * id in *series_id.  TB_ERR_BUDGET if it does not fit the HBM budget. */
+tb_status tb_load_series(tb_plan_t plan, const float* data, uint64_t n, double tsamp_s,
+                         uint32_t flags, int32_t* series_id);
+
+/* Frees a series; requests already submitted on it complete first. */
+tb_status tb_unload_series(tb_plan_t plan, int32_t series_id);
+
+/* Searches count templates of t over one resident series (Algorithm 1, then
+ * FFT, power, whitening, harmonic sum, threshold).  Asynchronous: the
+ * templates are copied before return and the work is queued on the plan's
+ * stream; *request_id names it for tb_poll / tb_get_candidates / tb_release.
+ * TB_ERR_INVALID_ARG for P_orb <= 0, tau < 0, e outside [0, 1) or
+ * non-finite values. */
+tb_status tb_search_templates(tb_plan_t plan, int32_t series_id, const tb_template* t,
+                              uint32_t count, uint32_t first_template_id, int64_t* request_id);
+
+/* TB_OK once the request's device work has finished, TB_ERR_NOT_READY before. */
+tb_status tb_poll(tb_plan_t plan, int64_t request_id);
+
+/* Copies up to capacity candidates of a request into out (host), sorted by
+ * (series, template, log2_harm, bin), and the full count into *n_total
+ * (out may be NULL to query the count).  blocking != 0 waits for the request;
+ * otherwise TB_ERR_NOT_READY is returned while it runs.  TB_ERR_OVERFLOW if
+ * the device ring overflowed (ring_capacity records are kept). */
+tb_status tb_get_candidates(tb_plan_t plan, int64_t request_id, tb_candidate* out,
+                            uint64_t capacity, uint64_t* n_total, int blocking);
+
+/* Waits for and forgets a request, freeing its device memory. */
+tb_status tb_release(tb_plan_t plan, int64_t request_id);
+
+/* Blocks until every queued request of the plan has finished. */
+tb_status tb_synchronize(tb_plan_t plan);
+
+/* Static description of a status. */
+const char* tb_strerror(tb_status status);
+
+/* Per-stage outputs of one template, for checking the stages one by one
+ * (same kernels as tb_search_templates).  Host buffers, any may be NULL:
+ *   src    int32[n]      input index read for output sample j (Algorithm 1)
+ *   power  float[n/2+1]  P_k = |X_k|^2 of the demodulated series
+ *   medians float[ceil((n/2)/W)]  whitening block medians
+ *   sums   float[(log2(harm_max)+1) * (n/2+1)]  S_h[k] per fold
+ * Candidates of this template are not kept. */
+tb_status tb_inspect_template(tb_plan_t plan, int32_t series_id, const tb_template* t,
+                              int32_t* src, float* power, float* medians, float* sums);
+
+/* Per-fold power thresholds the plan compares S_h against (float), for
+ * h = 1, 2, 4, 8, 16 (entries beyond harm_max are 0). */
+tb_status tb_thresholds(tb_plan_t plan, float out[5]);
+
+/* Milliseconds of device time of the last completed request's kernels, as
+ * measured with HIP events on the plan stream (0 if none). */
+tb_status tb_last_request_ms(tb_plan_t plan, int64_t request_id, double* ms);
+
+/* Per-kernel device timing: with profiling on, HIP events are recorded on the
+ * plan stream before, between and after the kernels of every wave.
+ * enable != 0 clears earlier measurements and starts a new one; 0 stops. */
+tb_status tb_profile(tb_plan_t plan, int enable);
+
+/* Waits for queued work and reports, per kernel class, the summed device
+ * milliseconds and launch counts since tb_profile(plan, 1):
+ *   [0] resample + FFT pass 1, [1] FFT pass 2 + power, [2] block medians,
+ *   [3] harmonic sum + threshold + compaction.
+ * *templates receives the number of templates those launches processed.
+ * Any output pointer may be NULL. */
+tb_status tb_profile_read(tb_plan_t plan, double ms[4], uint64_t launches[4], uint64_t* templates);
+
+/* Streaming copy of bytes (a multiple of 16) between two device buffers on the
+ * plan stream, repeated reps times; *ms receives the mean device time of one
+ * copy.  A measurement utility: the practical HBM ceiling. */
+tb_status tb_stream_copy(tb_plan_t plan, void* dst, const void* src, uint64_t bytes, uint32_t reps, double* ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,357 @@
+"""Python binding of libtb.so, the gfx950 template-bank coherent orbital search
+(arXiv:2112.11991) behind include/tb.h.
+
+Argument marshalling only: every step of the search runs in the library's HIP
+kernels.  Functions keep the C names (``tb_plan``, ``tb_load_series``,
+``tb_search_templates``, ``tb_get_candidates`` ...); :class:`Plan` wraps them
+for convenience.  Importing fails loudly when the library has not been built
+(``python paper_2112_11991_amd/build.py``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtb.so")
+
+TB_OK = 0
+TB_ERR_INVALID_ARG = -1
+TB_ERR_OOM = -2
+TB_ERR_BUDGET = -3
+TB_ERR_DEVICE = -4
+TB_ERR_OVERFLOW = -5
+TB_ERR_NOT_READY = -6
+TB_ERR_UNKNOWN_ID = -7
+TB_MEM_HOST = 0
+TB_MEM_DEVICE = 1
+
+
+class TbConfig(C.Structure):
+    _fields_ = [
+        ("max_log2n", C.c_uint32),
+        ("harm_max", C.c_uint32),
+        ("whiten_window", C.c_uint32),
+        ("batch_templates", C.c_uint32),
+        ("threshold_sigma", C.c_double),
+        ("fmin_hz", C.c_double),
+        ("fmax_hz", C.c_double),
+        ("hbm_budget_bytes", C.c_uint64),
+        ("ring_capacity", C.c_uint64),
+        ("stream", C.c_void_p),
+        ("device", C.c_int32),
+        ("flags", C.c_uint32),
+    ]
+
+
+class TbTemplate(C.Structure):
+    _fields_ = [
+        ("porb_s", C.c_double),
+        ("tau_lts", C.c_double),
+        ("alpha_rad", C.c_double),
+        ("ecc", C.c_double),
+        ("omega_rad", C.c_double),
+    ]
+
+
+TEMPLATE_DTYPE = np.dtype(
+    [("porb_s", "<f8"), ("tau_lts", "<f8"), ("alpha_rad", "<f8"), ("ecc", "<f8"), ("omega_rad", "<f8")]
+)
+CANDIDATE_DTYPE = np.dtype(
+    [
+        ("series_id", "<u4"),
+        ("template_id", "<u4"),
+        ("bin", "<u4"),
+        ("log2_harm", "u1"),
+        ("reserved", "u1", (3,)),
+        ("power", "<f4"),
+        ("sigma", "<f4"),
+        ("freq_hz", "<f8"),
+    ]
+)
+assert CANDIDATE_DTYPE.itemsize == 32 and TEMPLATE_DTYPE.itemsize == C.sizeof(TbTemplate) == 40
+assert C.sizeof(TbConfig) == 72
+
+EXPORTS = [
+    "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",
+    "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
+    "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy",
+]
+
+
+class TbError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (what, tb_strerror(status), status))
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libtb.so is not built at %s; run `python paper_2112_11991_amd/build.py` (hipcc, gfx950)" % LIB_PATH
+        )
+    L = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp, i32, u32, i64, u64 = C.c_void_p, C.c_int32, C.c_uint32, C.c_int64, C.c_uint64
+    L.tb_default_config.argtypes = [P(TbConfig)]
+    L.tb_default_config.restype = None
+    L.tb_plan.argtypes = [P(TbConfig), P(vp)]
+    L.tb_destroy.argtypes = [vp]
+    L.tb_load_series.argtypes = [vp, vp, u64, C.c_double, u32, P(i32)]
+    L.tb_unload_series.argtypes = [vp, i32]
+    L.tb_search_templates.argtypes = [vp, i32, vp, u32, u32, P(i64)]
+    L.tb_poll.argtypes = [vp, i64]
+    L.tb_get_candidates.argtypes = [vp, i64, vp, u64, P(u64), C.c_int]
+    L.tb_release.argtypes = [vp, i64]
+    L.tb_synchronize.argtypes = [vp]
+    L.tb_strerror.argtypes = [C.c_int]
+    L.tb_strerror.restype = C.c_char_p
+    L.tb_inspect_template.argtypes = [vp, i32, P(TbTemplate), vp, vp, vp, vp]
+    L.tb_thresholds.argtypes = [vp, vp]
+    L.tb_last_request_ms.argtypes = [vp, i64, P(C.c_double)]
+    L.tb_profile.argtypes = [vp, C.c_int]
+    L.tb_profile_read.argtypes = [vp, vp, vp, P(u64)]
+    L.tb_stream_copy.argtypes = [vp, vp, vp, u64, u32, P(C.c_double)]
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("tb_default_config", "tb_strerror"):
+            f.restype = C.c_int
+    return L
+
+
+_L = _load()
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return C.c_void_p(a)
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _check(st: int, what: str):
+    if st != TB_OK:
+        raise TbError(st, what)
+
+
+# ---------------------------------------------------------------- C names --
+def tb_default_config() -> TbConfig:
+    c = TbConfig()
+    _L.tb_default_config(C.byref(c))
+    return c
+
+
+def tb_strerror(status: int) -> str:
+    return _L.tb_strerror(int(status)).decode()
+
+
+def tb_plan(cfg: TbConfig) -> int:
+    h = C.c_void_p()
+    _check(_L.tb_plan(C.byref(cfg), C.byref(h)), "tb_plan")
+    return h.value
+
+
+def tb_destroy(plan: int) -> None:
+    _check(_L.tb_destroy(C.c_void_p(plan)), "tb_destroy")
+
+
+def tb_load_series(plan: int, data, tsamp: float, n: int | None = None, flags: int = TB_MEM_HOST) -> int:
+    """data: float32 numpy array (TB_MEM_HOST) or a device address (TB_MEM_DEVICE, n required)."""
+    sid = C.c_int32(-1)
+    if flags == TB_MEM_HOST:
+        data = np.ascontiguousarray(data, dtype=np.float32)
+        n = data.size
+    _check(_L.tb_load_series(C.c_void_p(plan), _ptr(data), int(n), float(tsamp), int(flags), C.byref(sid)),
+           "tb_load_series")
+    return sid.value
+
+
+def tb_unload_series(plan: int, series_id: int) -> None:
+    _check(_L.tb_unload_series(C.c_void_p(plan), int(series_id)), "tb_unload_series")
+
+
+def as_templates(templates) -> np.ndarray:
+    if isinstance(templates, np.ndarray) and templates.dtype.names == TEMPLATE_DTYPE.names:
+        return np.ascontiguousarray(templates.astype(TEMPLATE_DTYPE, copy=False))
+    arr = np.zeros(len(templates), dtype=TEMPLATE_DTYPE)
+    for i, t in enumerate(templates):
+        arr[i] = tuple(float(v) for v in t)
+    return arr
+
+
+def tb_search_templates(plan: int, series_id: int, templates, first_template_id: int = 0) -> int:
+    arr = as_templates(templates)
+    rid = C.c_int64(0)
+    _check(_L.tb_search_templates(C.c_void_p(plan), int(series_id), _ptr(arr), len(arr), int(first_template_id),
+                                  C.byref(rid)), "tb_search_templates")
+    return rid.value
+
+
+def tb_poll(plan: int, request_id: int) -> bool:
+    st = _L.tb_poll(C.c_void_p(plan), int(request_id))
+    if st == TB_ERR_NOT_READY:
+        return False
+    _check(st, "tb_poll")
+    return True
+
+
+def tb_get_candidates(plan: int, request_id: int, blocking: bool = True, allow_overflow: bool = False,
+                      ring_capacity: int | None = None):
+    """Returns (candidates structured array, n_total); None if not ready and
+    not blocking.  On overflow (allow_overflow) only the ring_capacity records
+    kept are returned."""
+    n = C.c_uint64(0)
+    st = _L.tb_get_candidates(C.c_void_p(plan), int(request_id), None, 0, C.byref(n), int(bool(blocking)))
+    if st == TB_ERR_NOT_READY and not blocking:
+        return None
+    if st not in (TB_OK, TB_ERR_OVERFLOW):
+        _check(st, "tb_get_candidates")
+    out = np.zeros(int(n.value), dtype=CANDIDATE_DTYPE)
+    st = _L.tb_get_candidates(C.c_void_p(plan), int(request_id), _ptr(out), out.size, C.byref(n), 1)
+    if st == TB_ERR_OVERFLOW and allow_overflow:
+        keep = out.size if ring_capacity is None else min(out.size, int(ring_capacity))
+        return out[:keep], int(n.value)
+    _check(st, "tb_get_candidates")
+    return out, int(n.value)
+
+
+def tb_release(plan: int, request_id: int) -> None:
+    _check(_L.tb_release(C.c_void_p(plan), int(request_id)), "tb_release")
+
+
+def tb_synchronize(plan: int) -> None:
+    _check(_L.tb_synchronize(C.c_void_p(plan)), "tb_synchronize")
+
+
+def tb_thresholds(plan: int) -> np.ndarray:
+    out = np.zeros(5, dtype=np.float32)
+    _check(_L.tb_thresholds(C.c_void_p(plan), _ptr(out)), "tb_thresholds")
+    return out
+
+
+def tb_last_request_ms(plan: int, request_id: int) -> float:
+    ms = C.c_double(0.0)
+    _check(_L.tb_last_request_ms(C.c_void_p(plan), int(request_id), C.byref(ms)), "tb_last_request_ms")
+    return ms.value
+
+
+def tb_profile(plan: int, enable: bool) -> None:
+    _check(_L.tb_profile(C.c_void_p(plan), int(bool(enable))), "tb_profile")
+
+
+def tb_profile_read(plan: int):
+    """(ms[4], launches[4], templates): pass 1, pass 2, medians, harmonic sum."""
+    ms = np.zeros(4, dtype=np.float64)
+    ln = np.zeros(4, dtype=np.uint64)
+    t = C.c_uint64(0)
+    _check(_L.tb_profile_read(C.c_void_p(plan), _ptr(ms), _ptr(ln), C.byref(t)), "tb_profile_read")
+    return ms, ln, int(t.value)
+
+
+def tb_stream_copy(plan: int, dst: int, src: int, nbytes: int, reps: int = 10) -> float:
+    ms = C.c_double(0.0)
+    _check(_L.tb_stream_copy(C.c_void_p(plan), C.c_void_p(dst), C.c_void_p(src), int(nbytes), int(reps),
+                             C.byref(ms)), "tb_stream_copy")
+    return ms.value
+
+
+def tb_inspect_template(plan: int, series_id: int, template, n: int, harm_max: int = 16, whiten_window: int = 4096,
+                        want=("src", "power", "medians", "sums")):
+    t = TbTemplate(*[float(v) for v in template])
+    nb = n // 2 + 1
+    nblk = (n // 2 + whiten_window - 1) // whiten_window
+    nf = int(harm_max).bit_length()
+    out = dict(
+        src=np.zeros(n, dtype=np.int32) if "src" in want else None,
+        power=np.zeros(nb, dtype=np.float32) if "power" in want else None,
+        medians=np.zeros(nblk, dtype=np.float32) if "medians" in want else None,
+        sums=np.zeros((nf, nb), dtype=np.float32) if "sums" in want else None,
+    )
+    _check(_L.tb_inspect_template(C.c_void_p(plan), int(series_id), C.byref(t), _ptr(out["src"]),
+                                  _ptr(out["power"]), _ptr(out["medians"]), _ptr(out["sums"])),
+           "tb_inspect_template")
+    return out
+
+
+# ------------------------------------------------------------- convenience --
+class Plan:
+    """Owns one tb_plan_t; keyword arguments override tb_default_config()."""
+
+    def __init__(self, **kw):
+        self.cfg = tb_default_config()
+        for k, v in kw.items():
+            if k == "stream":
+                v = C.c_void_p(int(v)) if v else None
+            setattr(self.cfg, k, v)
+        self.handle = tb_plan(self.cfg)
+        self.series_n = {}
+
+    def close(self):
+        if self.handle:
+            tb_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_series(self, data, tsamp, n=None, flags=TB_MEM_HOST) -> int:
+        sid = tb_load_series(self.handle, data, tsamp, n=n, flags=flags)
+        self.series_n[sid] = int(n if n is not None else np.asarray(data).size)
+        return sid
+
+    def unload_series(self, sid):
+        tb_unload_series(self.handle, sid)
+        self.series_n.pop(sid, None)
+
+    def submit(self, sid, templates, first_template_id=0) -> int:
+        return tb_search_templates(self.handle, sid, templates, first_template_id)
+
+    def poll(self, rid) -> bool:
+        return tb_poll(self.handle, rid)
+
+    def candidates(self, rid, blocking=True, allow_overflow=False):
+        return tb_get_candidates(self.handle, rid, blocking, allow_overflow, self.cfg.ring_capacity)
+
+    def release(self, rid):
+        tb_release(self.handle, rid)
+
+    def search(self, sid, templates, first_template_id=0):
+        """Submit, wait, fetch and release: the sorted candidate array."""
+        rid = self.submit(sid, templates, first_template_id)
+        try:
+            cands, _ = self.candidates(rid)
+        finally:
+            self.release(rid)
+        return cands
+
+    def inspect(self, sid, template, want=("src", "power", "medians", "sums")):
+        return tb_inspect_template(self.handle, sid, template, self.series_n[sid], self.cfg.harm_max,
+                                   self.cfg.whiten_window, want)
+
+    def thresholds(self):
+        return tb_thresholds(self.handle)
+
+    def synchronize(self):
+        tb_synchronize(self.handle)
+
+    def request_ms(self, rid) -> float:
+        return tb_last_request_ms(self.handle, rid)
+
+    def profile(self, enable=True):
+        tb_profile(self.handle, enable)
+
+    def profile_read(self):
+        return tb_profile_read(self.handle)

@@ -1,0 +1,839 @@
+// tb_engine.hip -- plan, resident series store, workspaces, request queue and
+// the C ABI of include/tb.h.  Host C++ on the HIP runtime; every step of the
+// search itself runs in the kernels of tb_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "tb_internal.h"
+
+using namespace tb;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Host statistics of the threshold step (Sec. 2.1).  Whitened noise powers
+// are unit exponentials, so a fold of h of them has the upper tail
+// Q(h, x) = exp(-x) sum_{k<h} x^k / k!.
+double log_q(int h, double x)
+{
+    if (x <= 0.0) return 0.0;
+    // log-sum-exp of log(x^k / k!) built incrementally
+    double lt = 0.0, mx = 0.0;
+    double terms[32];
+    for (int k = 0; k < h; ++k) {
+        if (k > 0) lt += std::log(x) - std::log((double)k);
+        terms[k] = lt;
+        mx = (k == 0 || lt > mx) ? lt : mx;
+    }
+    double acc = 0.0;
+    for (int k = 0; k < h; ++k) acc += std::exp(terms[k] - mx);
+    return -x + mx + std::log(acc);
+}
+
+// log of the one-sided Gaussian tail; beyond z = 8 via the continued fraction
+// of the Mills ratio.
+double log_gauss_sf(double z)
+{
+    if (z < 8.0) return std::log(0.5 * std::erfc(z / std::sqrt(2.0)));
+    double f = z;
+    for (int k = 80; k >= 1; --k) f = z + (double)k / f;
+    return -0.5 * z * z - 0.5 * std::log(2.0 * kPi) - std::log(f);
+}
+
+// Threshold x with log Q(h, x) = log_gauss_sf(sigma): bracket, then
+// Newton steps kept inside the bracket.
+double fold_threshold(int h, double sigma)
+{
+    double target = log_gauss_sf(sigma);
+    double lo = 0.0, hi = 8.0;
+    while (log_q(h, hi) > target) {
+        lo = hi;
+        hi *= 2.0;
+    }
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double g = log_q(h, x) - target;
+        if (g > 0) lo = x; else hi = x;
+        double dg = -std::exp((h - 1) * std::log(x) - x - std::lgamma((double)h) - log_q(h, x));
+        double nx = x - g / dg;
+        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+        if (std::fabs(nx - x) < 1e-13 * std::max(1.0, x)) {
+            x = nx;
+            break;
+        }
+        x = nx;
+    }
+    return x;
+}
+
+// Gaussian-equivalent significance of a fold power.
+double fold_sigma(int h, double s)
+{
+    double target = log_q(h, s);
+    if (target >= log_gauss_sf(-30.0)) return -30.0;
+    double lo = -30.0, hi = 10.0;
+    while (log_gauss_sf(hi) > target) {
+        lo = hi;
+        hi *= 2.0;
+    }
+    double z = std::sqrt(std::max(0.0, -2.0 * target));
+    if (!(z > lo && z < hi)) z = 0.5 * (lo + hi);
+    for (int it = 0; it < 200; ++it) {
+        double lz = log_gauss_sf(z);
+        double g = lz - target;
+        if (g > 0) lo = z; else hi = z;
+        double dg = -std::exp(-0.5 * z * z - 0.5 * std::log(2.0 * kPi) - lz);
+        double nz = z - g / dg;
+        if (!(nz > lo && nz < hi)) nz = 0.5 * (lo + hi);
+        if (std::fabs(nz - z) < 1e-12 * std::max(1.0, std::fabs(z))) {
+            z = nz;
+            break;
+        }
+        z = nz;
+    }
+    return z;
+}
+
+// ---------------------------------------------------------------------------
+struct SeriesRec {
+    int64_t n = 0;
+    double tsamp = 0;
+    float* d = nullptr;
+    size_t bytes = 0;
+};
+
+struct GeoRec {
+    Geometry g;
+    size_t bytes = 0;
+};
+
+struct SlotRec {
+    Slots s;
+    size_t bytes = 0;
+};
+
+struct Req {
+    int32_t series = -1;
+    uint32_t count = 0, first = 0;
+    uint64_t cap = 0;
+    int64_t n = 0;
+    double tsamp = 0;
+    char* dmem = nullptr;       // templates (device copy), prepared templates, counter, ring
+    tb_template* h_t = nullptr; // pinned host copy
+    size_t bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool fetched = false;
+    uint32_t total = 0;
+    std::vector<tb_candidate> cands;
+};
+
+}  // namespace
+
+struct tb_plan_s {
+    tb_config cfg;
+    hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;
+    bool own_stream = false;
+    std::mutex mu;
+    std::map<int32_t, SeriesRec> series;
+    std::map<int, GeoRec> geo;     // by log2 n
+    std::map<int, SlotRec> slots;  // by log2 n
+    std::map<int64_t, Req> reqs;
+    int32_t next_series = 0;
+    int64_t next_req = 1;
+    uint64_t held = 0;
+    double thr[5] = {0, 0, 0, 0, 0};
+    double* d_partial = nullptr;
+    bool profiling = false;
+    std::vector<std::vector<hipEvent_t>> prof_events;  // K_CLASSES + 1 per wave
+    uint64_t prof_templates = 0;
+};
+
+namespace {
+
+#define TB_TRY(call)                                   \
+    do {                                               \
+        if ((call) != hipSuccess) return TB_ERR_DEVICE; \
+    } while (0)
+
+bool pow2(uint64_t v) { return v && !(v & (v - 1)); }
+int ilog2(uint64_t v)
+{
+    int l = 0;
+    while ((1ull << l) < v) ++l;
+    return l;
+}
+
+tb_status reserve(tb_plan_t p, size_t bytes)
+{
+    if (p->cfg.hbm_budget_bytes && p->held + bytes > p->cfg.hbm_budget_bytes) return TB_ERR_BUDGET;
+    p->held += bytes;
+    return TB_OK;
+}
+
+tb_status upload_table(std::vector<float2>& h, float2** d, size_t* bytes)
+{
+    size_t b = h.size() * sizeof(float2);
+    if (hipMalloc(d, b) != hipSuccess) return TB_ERR_OOM;
+    TB_TRY(hipMemcpy(*d, h.data(), b, hipMemcpyHostToDevice));
+    *bytes += b;
+    return TB_OK;
+}
+
+// exp(-2 pi i r num / den) for r < count, in FP64 then rounded.
+std::vector<float2> twiddles(int64_t count, double num, double den)
+{
+    std::vector<float2> t((size_t)count);
+    for (int64_t r = 0; r < count; ++r) {
+        double a = -2.0 * kPi * ((double)r * num) / den;
+        t[(size_t)r] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    return t;
+}
+
+tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
+{
+    auto it = p->geo.find(log2n);
+    if (it != p->geo.end()) {
+        *out = &it->second.g;
+        return TB_OK;
+    }
+    GeoRec rec;
+    Geometry& g = rec.g;
+    g.log2n = log2n;
+    g.n = (int64_t)1 << log2n;
+    g.M = g.n / 2;
+    int m = log2n - 1;
+    g.S = 1 << ((m + 1) / 2);
+    g.R = 1 << (m / 2);
+    g.C1 = pass1_columns(g.S);
+    g.D = pass2_pairs(g.R);
+    g.W = (int)p->cfg.whiten_window;
+    g.nblk = (int)((g.M + g.W - 1) / g.W);
+    g.htile = harmsum_tile();
+    int64_t hi = std::max<int64_t>(1, g.M >> TW_LO_BITS);
+    std::vector<float2> v;
+    tb_status st;
+    v = twiddles(g.S, 1.0, (double)g.S);
+    if ((st = upload_table(v, &g.twS, &rec.bytes))) return st;
+    v = twiddles(g.R, 1.0, (double)g.R);
+    if ((st = upload_table(v, &g.twR, &rec.bytes))) return st;
+    v = twiddles(1 << TW_LO_BITS, 1.0, (double)g.M);
+    if ((st = upload_table(v, &g.twM_lo, &rec.bytes))) return st;
+    v = twiddles(hi, (double)(1 << TW_LO_BITS), (double)g.M);
+    if ((st = upload_table(v, &g.twM_hi, &rec.bytes))) return st;
+    v = twiddles(1 << TW_LO_BITS, 1.0, 2.0 * (double)g.M);
+    if ((st = upload_table(v, &g.tw2M_lo, &rec.bytes))) return st;
+    v = twiddles(hi, (double)(1 << TW_LO_BITS), 2.0 * (double)g.M);
+    if ((st = upload_table(v, &g.tw2M_hi, &rec.bytes))) return st;
+    p->held += rec.bytes;
+    auto ins = p->geo.emplace(log2n, rec);
+    *out = &ins.first->second.g;
+    return TB_OK;
+}
+
+void free_geometry(GeoRec& r)
+{
+    hipFree(r.g.twS);
+    hipFree(r.g.twR);
+    hipFree(r.g.twM_lo);
+    hipFree(r.g.twM_hi);
+    hipFree(r.g.tw2M_lo);
+    hipFree(r.g.tw2M_hi);
+}
+
+int default_batch(const tb_plan_t p, int64_t M)
+{
+    if (p->cfg.batch_templates) return (int)p->cfg.batch_templates;
+    int64_t b = ((int64_t)1 << 25) / M;
+    return (int)std::min<int64_t>(256, std::max<int64_t>(4, b));
+}
+
+tb_status get_slots(tb_plan_t p, const Geometry& g, Slots** out)
+{
+    auto it = p->slots.find(g.log2n);
+    if (it != p->slots.end()) {
+        *out = &it->second.s;
+        return TB_OK;
+    }
+    SlotRec rec;
+    Slots& s = rec.s;
+    s.B = default_batch(p, g.M);
+    s.y_stride = (size_t)g.M;
+    s.p_stride = ((size_t)g.M + 1 + 63) & ~(size_t)63;
+    s.med_stride = ((size_t)g.nblk + 63) & ~(size_t)63;
+    size_t by = sizeof(float2) * s.y_stride * s.B, bp = sizeof(float) * s.p_stride * s.B,
+           bm = sizeof(float) * s.med_stride * s.B;
+    rec.bytes = by + bp + bm;
+    tb_status st = reserve(p, rec.bytes);
+    if (st) return st;
+    if (hipMalloc(&s.Y, by) != hipSuccess || hipMalloc(&s.P, bp) != hipSuccess ||
+        hipMalloc(&s.med, bm) != hipSuccess) {
+        hipFree(s.Y);
+        hipFree(s.P);
+        hipFree(s.med);
+        p->held -= rec.bytes;
+        return TB_ERR_OOM;
+    }
+    auto ins = p->slots.emplace(g.log2n, rec);
+    *out = &ins.first->second.s;
+    return TB_OK;
+}
+
+PeakParams peak_params(tb_plan_t p, int64_t n, double tsamp, uint32_t series_id, uint32_t first, uint64_t cap)
+{
+    PeakParams pp;
+    std::memset(&pp, 0, sizeof(pp));
+    int64_t M = n / 2;
+    double T = (double)n * tsamp;
+    int64_t kmin = (int64_t)std::ceil(p->cfg.fmin_hz * T);
+    if (kmin < 1) kmin = 1;
+    pp.nfold = ilog2(p->cfg.harm_max) + 1;
+    for (int l = 0; l < 5; ++l) {
+        int64_t h = (int64_t)1 << l;
+        pp.thr[l] = (float)p->thr[l];
+        pp.klo[l] = (int32_t)std::min<int64_t>(M + 1, h * kmin);
+        int64_t khi = M;
+        if (p->cfg.fmax_hz > 0.0) khi = std::min<int64_t>(M, (int64_t)std::floor((double)h * p->cfg.fmax_hz * T));
+        pp.khi[l] = (int32_t)std::max<int64_t>(-1, khi);
+    }
+    pp.series_id = series_id;
+    pp.first_template_id = first;
+    pp.capacity = (uint32_t)std::min<uint64_t>(cap, 0xffffffffull);
+    return pp;
+}
+
+bool valid_template(const tb_template& t)
+{
+    return std::isfinite(t.porb_s) && std::isfinite(t.tau_lts) && std::isfinite(t.alpha_rad) &&
+           std::isfinite(t.ecc) && std::isfinite(t.omega_rad) && t.porb_s > 0.0 && t.tau_lts >= 0.0 &&
+           t.ecc >= 0.0 && t.ecc < 1.0;
+}
+
+void free_request(Req& r)
+{
+    if (r.ev0) hipEventDestroy(r.ev0);
+    if (r.ev1) hipEventDestroy(r.ev1);
+    hipFree(r.dmem);
+    hipHostFree(r.h_t);
+    r.dmem = nullptr;
+    r.h_t = nullptr;
+}
+
+struct ReqLayout {
+    size_t off_t, off_tm, off_cnt, off_ring, total;
+};
+
+ReqLayout req_layout(uint32_t count, uint64_t cap)
+{
+    ReqLayout L;
+    L.off_t = 0;
+    L.off_tm = ((size_t)count * sizeof(tb_template) + 255) & ~(size_t)255;
+    L.off_cnt = L.off_tm + (((size_t)count * sizeof(TmplDev) + 255) & ~(size_t)255);
+    L.off_ring = L.off_cnt + 256;
+    L.total = L.off_ring + (size_t)cap * sizeof(uint4);
+    return L;
+}
+
+// Queue the kernels of all templates of a request, wave by wave.
+tb_status enqueue(tb_plan_t p, const SeriesRec& sr, Geometry* g, Slots* ws, const TmplDev* d_tm, uint32_t count,
+                  const PeakParams& pp, uint4* ring, uint32_t* counter, const Inspect& ins)
+{
+    for (uint32_t w0 = 0; w0 < count; w0 += (uint32_t)ws->B) {
+        int nslots = (int)std::min<uint32_t>((uint32_t)ws->B, count - w0);
+        hipEvent_t* ev = nullptr;
+        if (p->profiling) {
+            std::vector<hipEvent_t> evs(K_CLASSES + 1, nullptr);
+            for (auto& e : evs)
+                if (hipEventCreate(&e) != hipSuccess) return TB_ERR_DEVICE;
+            p->prof_events.push_back(std::move(evs));
+            ev = p->prof_events.back().data();
+            p->prof_templates += (uint64_t)nslots;
+        }
+        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, pp, ring, counter, ins, p->stream, ev) !=
+            hipSuccess)
+            return TB_ERR_DEVICE;
+    }
+    return TB_OK;
+}
+
+tb_status fetch(tb_plan_t p, Req& r)
+{
+    if (r.fetched) return TB_OK;
+    ReqLayout L = req_layout(r.count, r.cap);
+    uint32_t total = 0;
+    TB_TRY(hipMemcpyAsync(&total, r.dmem + L.off_cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, p->copy_stream));
+    TB_TRY(hipStreamSynchronize(p->copy_stream));
+    uint64_t keep = std::min<uint64_t>(total, r.cap);
+    std::vector<uint4> raw((size_t)keep);
+    if (keep) {
+        TB_TRY(hipMemcpyAsync(raw.data(), r.dmem + L.off_ring, keep * sizeof(uint4), hipMemcpyDeviceToHost,
+                              p->copy_stream));
+        TB_TRY(hipStreamSynchronize(p->copy_stream));
+    }
+    double T = (double)r.n * r.tsamp;
+    r.cands.resize((size_t)keep);
+    for (size_t i = 0; i < keep; ++i) {
+        const uint4& q = raw[i];
+        tb_candidate& c = r.cands[i];
+        std::memset(&c, 0, sizeof(c));
+        c.template_id = q.x;
+        c.bin = q.y;
+        c.series_id = q.z >> 8;
+        c.log2_harm = (uint8_t)(q.z & 0xff);
+        float pw;
+        std::memcpy(&pw, &q.w, sizeof(pw));
+        c.power = pw;
+        int h = 1 << c.log2_harm;
+        c.sigma = (float)fold_sigma(h, (double)pw);
+        c.freq_hz = (double)c.bin / ((double)h * T);
+    }
+    std::sort(r.cands.begin(), r.cands.end(), [](const tb_candidate& a, const tb_candidate& b) {
+        if (a.series_id != b.series_id) return a.series_id < b.series_id;
+        if (a.template_id != b.template_id) return a.template_id < b.template_id;
+        if (a.log2_harm != b.log2_harm) return a.log2_harm < b.log2_harm;
+        return a.bin < b.bin;
+    });
+    r.total = total;
+    r.fetched = true;
+    return TB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tb_default_config(tb_config* c)
+{
+    if (!c) return;
+    std::memset(c, 0, sizeof(*c));
+    c->max_log2n = 24;
+    c->harm_max = 16;
+    c->whiten_window = 4096;
+    c->batch_templates = 0;
+    c->threshold_sigma = 6.0;
+    c->fmin_hz = 1.0;
+    c->fmax_hz = 0.0;
+    c->hbm_budget_bytes = 0;
+    c->ring_capacity = 1u << 20;
+    c->stream = nullptr;
+    c->device = 0;
+    c->flags = 0;
+}
+
+const char* tb_strerror(tb_status s)
+{
+    switch (s) {
+    case TB_OK: return "ok";
+    case TB_ERR_INVALID_ARG: return "invalid argument";
+    case TB_ERR_OOM: return "out of memory";
+    case TB_ERR_BUDGET: return "HBM budget exceeded";
+    case TB_ERR_DEVICE: return "HIP runtime error";
+    case TB_ERR_OVERFLOW: return "candidate ring overflowed";
+    case TB_ERR_NOT_READY: return "not ready";
+    case TB_ERR_UNKNOWN_ID: return "unknown id";
+    }
+    return "unknown status";
+}
+
+tb_status tb_plan(const tb_config* cfg, tb_plan_t* out)
+{
+    if (!cfg || !out) return TB_ERR_INVALID_ARG;
+    *out = nullptr;
+    const tb_config& c = *cfg;
+    if (c.max_log2n < 10 || c.max_log2n > 24) return TB_ERR_INVALID_ARG;
+    if (c.harm_max != 1 && c.harm_max != 2 && c.harm_max != 4 && c.harm_max != 8 && c.harm_max != 16)
+        return TB_ERR_INVALID_ARG;
+    if (c.whiten_window < 1 || c.whiten_window > 8192) return TB_ERR_INVALID_ARG;
+    if (!std::isfinite(c.threshold_sigma) || !std::isfinite(c.fmin_hz) || !std::isfinite(c.fmax_hz) ||
+        c.fmin_hz < 0.0 || c.fmax_hz < 0.0)
+        return TB_ERR_INVALID_ARG;
+    if (c.ring_capacity == 0 || c.ring_capacity > 0xffffffffull || c.batch_templates > 4096 || c.flags)
+        return TB_ERR_INVALID_ARG;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev) return TB_ERR_DEVICE;
+    if (hipSetDevice(c.device) != hipSuccess) return TB_ERR_DEVICE;
+    tb_plan_t p = new (std::nothrow) tb_plan_s();
+    if (!p) return TB_ERR_OOM;
+    p->cfg = c;
+    if (c.stream) {
+        p->stream = (hipStream_t)c.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete p;
+            return TB_ERR_DEVICE;
+        }
+        p->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipMalloc(&p->d_partial, sizeof(double) * 1040) != hipSuccess) {
+        if (p->own_stream) hipStreamDestroy(p->stream);
+        if (p->copy_stream) hipStreamDestroy(p->copy_stream);
+        delete p;
+        return TB_ERR_DEVICE;
+    }
+    for (int l = 0; l < 5; ++l) p->thr[l] = (1u << l) <= c.harm_max ? fold_threshold(1 << l, c.threshold_sigma) : 0.0;
+    *out = p;
+    return TB_OK;
+}
+
+tb_status tb_destroy(tb_plan_t p)
+{
+    if (!p) return TB_OK;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        hipSetDevice(p->cfg.device);
+        hipStreamSynchronize(p->stream);
+        for (auto& kv : p->reqs) free_request(kv.second);
+        for (auto& kv : p->series) hipFree(kv.second.d);
+        for (auto& kv : p->slots) {
+            hipFree(kv.second.s.Y);
+            hipFree(kv.second.s.P);
+            hipFree(kv.second.s.med);
+        }
+        for (auto& kv : p->geo) free_geometry(kv.second);
+        for (auto& v : p->prof_events)
+            for (auto e : v) hipEventDestroy(e);
+        hipFree(p->d_partial);
+        hipStreamDestroy(p->copy_stream);
+        if (p->own_stream) hipStreamDestroy(p->stream);
+    }
+    delete p;
+    return TB_OK;
+}
+
+tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsamp, uint32_t flags, int32_t* id)
+{
+    if (!p || !data || !id || !pow2(n) || n < 1024 || n > (1ull << p->cfg.max_log2n) || !(tsamp > 0.0) ||
+        !std::isfinite(tsamp) || (flags != TB_MEM_HOST && flags != TB_MEM_DEVICE))
+        return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    TB_TRY(hipSetDevice(p->cfg.device));
+    if (p->next_series >= (1 << 24)) return TB_ERR_INVALID_ARG;
+    SeriesRec r;
+    r.n = (int64_t)n;
+    r.tsamp = tsamp;
+    r.bytes = sizeof(float) * n;
+    tb_status st = reserve(p, r.bytes);
+    if (st) return st;
+    if (hipMalloc(&r.d, r.bytes) != hipSuccess) {
+        p->held -= r.bytes;
+        return TB_ERR_OOM;
+    }
+    const float* src = data;
+    float* staging = nullptr;
+    if (flags == TB_MEM_HOST) {
+        if (hipMalloc(&staging, r.bytes) != hipSuccess ||
+            hipMemcpyAsync(staging, data, r.bytes, hipMemcpyHostToDevice, p->stream) != hipSuccess) {
+            hipFree(staging);
+            hipFree(r.d);
+            p->held -= r.bytes;
+            return TB_ERR_DEVICE;
+        }
+        src = staging;
+    }
+    hipError_t e = launch_mean_subtract(src, r.d, r.n, p->d_partial, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    hipFree(staging);
+    if (e != hipSuccess) {
+        hipFree(r.d);
+        p->held -= r.bytes;
+        return TB_ERR_DEVICE;
+    }
+    *id = p->next_series++;
+    p->series.emplace(*id, r);
+    return TB_OK;
+}
+
+tb_status tb_unload_series(tb_plan_t p, int32_t id)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->series.find(id);
+    if (it == p->series.end()) return TB_ERR_UNKNOWN_ID;
+    TB_TRY(hipSetDevice(p->cfg.device));
+    TB_TRY(hipStreamSynchronize(p->stream));
+    hipFree(it->second.d);
+    p->held -= it->second.bytes;
+    p->series.erase(it);
+    return TB_OK;
+}
+
+tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, uint32_t count, uint32_t first,
+                              int64_t* request_id)
+{
+    if (!p || !request_id || (count && !t)) return TB_ERR_INVALID_ARG;
+    for (uint32_t i = 0; i < count; ++i)
+        if (!valid_template(t[i])) return TB_ERR_INVALID_ARG;
+    if ((uint64_t)first + count > 0xffffffffull) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto sit = p->series.find(sid);
+    if (sit == p->series.end()) return TB_ERR_UNKNOWN_ID;
+    TB_TRY(hipSetDevice(p->cfg.device));
+    const SeriesRec& sr = sit->second;
+    Geometry* g = nullptr;
+    Slots* ws = nullptr;
+    tb_status st;
+    if ((st = get_geometry(p, ilog2((uint64_t)sr.n), &g))) return st;
+    if ((st = get_slots(p, *g, &ws))) return st;
+
+    Req r;
+    r.series = sid;
+    r.count = count;
+    r.first = first;
+    r.cap = p->cfg.ring_capacity;
+    r.n = sr.n;
+    r.tsamp = sr.tsamp;
+    ReqLayout L = req_layout(count, r.cap);
+    r.bytes = L.total;
+    if ((st = reserve(p, r.bytes))) return st;
+    if (hipMalloc(&r.dmem, L.total) != hipSuccess) {
+        p->held -= r.bytes;
+        return TB_ERR_OOM;
+    }
+    if (count && hipHostMalloc(&r.h_t, sizeof(tb_template) * count, hipHostMallocDefault) != hipSuccess) {
+        free_request(r);
+        p->held -= r.bytes;
+        return TB_ERR_OOM;
+    }
+    if (count) std::memcpy(r.h_t, t, sizeof(tb_template) * count);
+    tb_template* d_t = (tb_template*)(r.dmem + L.off_t);
+    TmplDev* d_tm = (TmplDev*)(r.dmem + L.off_tm);
+    uint32_t* counter = (uint32_t*)(r.dmem + L.off_cnt);
+    uint4* ring = (uint4*)(r.dmem + L.off_ring);
+    PeakParams pp = peak_params(p, sr.n, sr.tsamp, (uint32_t)sid, first, r.cap);
+    if (hipEventCreate(&r.ev0) != hipSuccess || hipEventCreate(&r.ev1) != hipSuccess ||
+        hipEventRecord(r.ev0, p->stream) != hipSuccess || launch_fill_u32(counter, 0u, 1, p->stream) != hipSuccess ||
+        (count && hipMemcpyAsync(d_t, r.h_t, sizeof(tb_template) * count, hipMemcpyHostToDevice, p->stream) !=
+                      hipSuccess) ||
+        launch_template_prep(d_t, count, d_tm, p->stream) != hipSuccess) {
+        free_request(r);
+        p->held -= r.bytes;
+        return TB_ERR_DEVICE;
+    }
+    Inspect none;
+    st = enqueue(p, sr, g, ws, d_tm, count, pp, ring, counter, none);
+    if (st == TB_OK && hipEventRecord(r.ev1, p->stream) != hipSuccess) st = TB_ERR_DEVICE;
+    if (st) {
+        hipStreamSynchronize(p->stream);
+        free_request(r);
+        p->held -= r.bytes;
+        return st;
+    }
+    int64_t rid = p->next_req++;
+    p->reqs.emplace(rid, std::move(r));
+    *request_id = rid;
+    return TB_OK;
+}
+
+tb_status tb_poll(tb_plan_t p, int64_t rid)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->reqs.find(rid);
+    if (it == p->reqs.end()) return TB_ERR_UNKNOWN_ID;
+    hipError_t e = hipEventQuery(it->second.ev1);
+    if (e == hipSuccess) return TB_OK;
+    if (e == hipErrorNotReady) return TB_ERR_NOT_READY;
+    return TB_ERR_DEVICE;
+}
+
+tb_status tb_get_candidates(tb_plan_t p, int64_t rid, tb_candidate* out, uint64_t capacity, uint64_t* n_total,
+                            int blocking)
+{
+    if (!p || !n_total) return TB_ERR_INVALID_ARG;
+    hipEvent_t ev;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        auto it = p->reqs.find(rid);
+        if (it == p->reqs.end()) return TB_ERR_UNKNOWN_ID;
+        ev = it->second.ev1;
+        if (!it->second.fetched) {
+            hipError_t e = hipEventQuery(ev);
+            if (e == hipErrorNotReady && !blocking) return TB_ERR_NOT_READY;
+            if (e != hipSuccess && e != hipErrorNotReady) return TB_ERR_DEVICE;
+        }
+    }
+    TB_TRY(hipSetDevice(p->cfg.device));
+    TB_TRY(hipEventSynchronize(ev));
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->reqs.find(rid);
+    if (it == p->reqs.end()) return TB_ERR_UNKNOWN_ID;
+    Req& r = it->second;
+    tb_status st = fetch(p, r);
+    if (st) return st;
+    *n_total = r.total;
+    if (out) {
+        size_t k = (size_t)std::min<uint64_t>(capacity, r.cands.size());
+        if (k) std::memcpy(out, r.cands.data(), k * sizeof(tb_candidate));
+    }
+    return r.total > r.cap ? TB_ERR_OVERFLOW : TB_OK;
+}
+
+tb_status tb_release(tb_plan_t p, int64_t rid)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->reqs.find(rid);
+    if (it == p->reqs.end()) return TB_ERR_UNKNOWN_ID;
+    TB_TRY(hipSetDevice(p->cfg.device));
+    TB_TRY(hipEventSynchronize(it->second.ev1));
+    p->held -= it->second.bytes;
+    free_request(it->second);
+    p->reqs.erase(it);
+    return TB_OK;
+}
+
+tb_status tb_synchronize(tb_plan_t p)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    TB_TRY(hipSetDevice(p->cfg.device));
+    TB_TRY(hipStreamSynchronize(p->stream));
+    return TB_OK;
+}
+
+tb_status tb_thresholds(tb_plan_t p, float out[5])
+{
+    if (!p || !out) return TB_ERR_INVALID_ARG;
+    for (int l = 0; l < 5; ++l) out[l] = (float)p->thr[l];
+    return TB_OK;
+}
+
+tb_status tb_last_request_ms(tb_plan_t p, int64_t rid, double* ms)
+{
+    if (!p || !ms) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->reqs.find(rid);
+    if (it == p->reqs.end()) return TB_ERR_UNKNOWN_ID;
+    TB_TRY(hipEventSynchronize(it->second.ev1));
+    float f = 0.0f;
+    TB_TRY(hipEventElapsedTime(&f, it->second.ev0, it->second.ev1));
+    *ms = f;
+    return TB_OK;
+}
+
+tb_status tb_profile(tb_plan_t p, int enable)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (enable) {
+        TB_TRY(hipSetDevice(p->cfg.device));
+        TB_TRY(hipStreamSynchronize(p->stream));
+        for (auto& v : p->prof_events)
+            for (auto e : v) hipEventDestroy(e);
+        p->prof_events.clear();
+        p->prof_templates = 0;
+    }
+    p->profiling = enable != 0;
+    return TB_OK;
+}
+
+tb_status tb_profile_read(tb_plan_t p, double ms[4], uint64_t launches[4], uint64_t* templates)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    TB_TRY(hipSetDevice(p->cfg.device));
+    TB_TRY(hipStreamSynchronize(p->stream));
+    double acc[K_CLASSES] = {0, 0, 0, 0};
+    for (auto& v : p->prof_events)
+        for (int k = 0; k < K_CLASSES; ++k) {
+            float f = 0.0f;
+            TB_TRY(hipEventElapsedTime(&f, v[k], v[k + 1]));
+            acc[k] += f;
+        }
+    for (int k = 0; k < K_CLASSES; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (launches) launches[k] = p->prof_events.size();
+    }
+    if (templates) *templates = p->prof_templates;
+    return TB_OK;
+}
+
+tb_status tb_stream_copy(tb_plan_t p, void* dst, const void* src, uint64_t bytes, uint32_t reps, double* ms)
+{
+    if (!p || !dst || !src || !ms || bytes == 0 || (bytes & 15) || reps == 0) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    TB_TRY(hipSetDevice(p->cfg.device));
+    hipEvent_t a = nullptr, b = nullptr;
+    TB_TRY(hipEventCreate(&a));
+    TB_TRY(hipEventCreate(&b));
+    hipError_t e = launch_copy((float4*)dst, (const float4*)src, bytes / 16, p->stream);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, p->stream);
+    for (uint32_t r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy((float4*)dst, (const float4*)src, bytes / 16, p->stream);
+    if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float f = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (e != hipSuccess) return TB_ERR_DEVICE;
+    *ms = (double)f / reps;
+    return TB_OK;
+}
+
+tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, int32_t* src, float* power,
+                              float* medians, float* sums)
+{
+    if (!p || !t || !valid_template(*t)) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto sit = p->series.find(sid);
+    if (sit == p->series.end()) return TB_ERR_UNKNOWN_ID;
+    TB_TRY(hipSetDevice(p->cfg.device));
+    const SeriesRec& sr = sit->second;
+    Geometry* g = nullptr;
+    Slots* ws = nullptr;
+    tb_status st;
+    if ((st = get_geometry(p, ilog2((uint64_t)sr.n), &g))) return st;
+    if ((st = get_slots(p, *g, &ws))) return st;
+    int nfold = ilog2(p->cfg.harm_max) + 1;
+    size_t nb = (size_t)g->M + 1;
+    size_t need = 256 + 256 + sizeof(uint4) * 16 + sizeof(int32_t) * (size_t)sr.n + sizeof(float) * nfold * nb;
+    char* d = nullptr;
+    tb_template* ht = nullptr;
+    if (hipMalloc(&d, need) != hipSuccess) return TB_ERR_OOM;
+    if (hipHostMalloc(&ht, sizeof(tb_template), hipHostMallocDefault) != hipSuccess) {
+        hipFree(d);
+        return TB_ERR_OOM;
+    }
+    *ht = *t;
+    TmplDev* d_tm = (TmplDev*)d;
+    tb_template* d_t = (tb_template*)(d + 128);
+    uint32_t* counter = (uint32_t*)(d + 256);
+    uint4* ring = (uint4*)(d + 512);
+    Inspect ins;
+    ins.src = (int32_t*)(d + 512 + sizeof(uint4) * 16);
+    ins.sums = (float*)((char*)ins.src + sizeof(int32_t) * (size_t)sr.n);
+    PeakParams pp = peak_params(p, sr.n, sr.tsamp, (uint32_t)sid, 0, 0);
+    st = TB_OK;
+    if (launch_fill_u32(counter, 0u, 1, p->stream) != hipSuccess ||
+        hipMemcpyAsync(d_t, ht, sizeof(tb_template), hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+        launch_template_prep(d_t, 1, d_tm, p->stream) != hipSuccess)
+        st = TB_ERR_DEVICE;
+    if (!st) st = enqueue(p, sr, g, ws, d_tm, 1, pp, ring, counter, ins);
+    if (!st && hipStreamSynchronize(p->stream) != hipSuccess) st = TB_ERR_DEVICE;
+    if (!st && src && hipMemcpy(src, ins.src, sizeof(int32_t) * (size_t)sr.n, hipMemcpyDeviceToHost) != hipSuccess)
+        st = TB_ERR_DEVICE;
+    if (!st && power && hipMemcpy(power, ws->P, sizeof(float) * nb, hipMemcpyDeviceToHost) != hipSuccess)
+        st = TB_ERR_DEVICE;
+    if (!st && medians &&
+        hipMemcpy(medians, ws->med, sizeof(float) * (size_t)g->nblk, hipMemcpyDeviceToHost) != hipSuccess)
+        st = TB_ERR_DEVICE;
+    if (!st && sums && hipMemcpy(sums, ins.sums, sizeof(float) * nfold * nb, hipMemcpyDeviceToHost) != hipSuccess)
+        st = TB_ERR_DEVICE;
+    hipStreamSynchronize(p->stream);
+    hipFree(d);
+    hipHostFree(ht);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// tb_internal.h -- declarations shared by the kernels and the engine of the
+// gfx950 template-bank search library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tb.h"
+
+namespace tb {
+
+// Per-template constants, prepared on the device from a tb_template:
+// Omega = 2 pi / P_orb, the Roemer-delay factors of the BT model (App. A.1)
+// and the zero offset Delta(0) of Algorithm 1.
+struct TmplDev {
+    double omega, alpha, tau, ecc;
+    double sinw, cosw, beta, d0;
+};
+static_assert(sizeof(TmplDev) == 64, "TmplDev layout");
+
+// Two-pass FFT geometry of a real series of n = 2M samples packed as M
+// complex points, M = R * S.  Pass 1 does S-point transforms over the strided
+// index (C1 columns per workgroup), pass 2 R-point transforms (D mirrored
+// column pairs per workgroup) followed by the real-to-complex split and |X|^2.
+struct Geometry {
+    int log2n = 0;
+    int64_t n = 0, M = 0;
+    int S = 0, R = 0, C1 = 0, D = 0;
+    int W = 0;             // whitening window (bins per median block)
+    int nblk = 0;          // whitening blocks
+    int htile = 0;         // harmonic-sum output bins per workgroup
+    float2* twS = nullptr; // W_S^r, r < S
+    float2* twR = nullptr; // W_R^r, r < R
+    float2* twM_lo = nullptr, *twM_hi = nullptr;   // W_M^q split in 2^10 x rest
+    float2* tw2M_lo = nullptr, *tw2M_hi = nullptr; // W_2M^k likewise
+};
+
+constexpr int TW_LO_BITS = 10;
+
+// Per-launch search parameters of the harmonic sum / threshold stage.
+struct PeakParams {
+    float thr[5];      // S_h threshold per fold, h = 1, 2, 4, 8, 16
+    int32_t klo[5];    // first bin searched per fold (h * kmin)
+    int32_t khi[5];    // last bin searched per fold
+    int32_t nfold;     // log2(harm_max) + 1
+    uint32_t series_id;
+    uint32_t first_template_id;
+    uint32_t capacity; // ring records
+};
+
+// Device workspace for B templates in flight at one series length.
+struct Slots {
+    int B = 0;
+    float2* Y = nullptr;   // exchange buffer, B x M complex
+    size_t y_stride = 0;   // complex per slot
+    float* P = nullptr;    // power, B x (M + 1), padded
+    size_t p_stride = 0;
+    float* med = nullptr;  // block medians, B x nblk
+    size_t med_stride = 0;
+};
+
+// Optional per-stage outputs (template slot 0 only).
+struct Inspect {
+    int32_t* src = nullptr;  // n
+    float* sums = nullptr;   // nfold x (M + 1)
+};
+
+hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, hipStream_t s);
+hipError_t launch_mean_subtract(const float* in, float* out, int64_t n, double* partial, hipStream_t s);
+// Kernel classes timed by the plan's profiler.
+enum { K_PASS1 = 0, K_PASS2 = 1, K_MEDIAN = 2, K_HARMSUM = 3, K_CLASSES = 4 };
+
+// Queues the four kernels of one wave of nslots templates.  ev, if not null,
+// holds K_CLASSES + 1 events recorded before, between and after them.
+hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
+                       int nslots, const Slots& ws, const PeakParams& pp, uint4* ring, uint32_t* counter,
+                       const Inspect& ins, hipStream_t s, hipEvent_t* ev = nullptr);
+hipError_t launch_copy(float4* dst, const float4* src, size_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
+int pass1_columns(int S);
+int pass2_pairs(int R);
+int harmsum_tile();
+
+}  // namespace tb
