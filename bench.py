@@ -56,8 +56,7 @@ def describe(w, name):
                 "templates": int(len(w.templates))}
     kind = "elliptical" if w.templates["ecc"].max() > 0 else "circular"
     return {"workload": "%s search: one series N=2^%d at %g us, %d uniform %s templates, 16 harmonics, 6 sigma, "
-                        "whitening W=4096" % (w.name, int(math.log2(n[0])), w.tsamp * 1e6, len(w.templates), kind,
-                                              kind),
+                        "whitening W=4096" % (w.name, int(math.log2(n[0])), w.tsamp * 1e6, len(w.templates), kind),
             "n": n[0], "tsamp_s": w.tsamp, "templates": int(len(w.templates)), "harmonics": 16,
             "whiten_window": 4096}
 

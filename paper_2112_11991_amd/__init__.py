@@ -88,6 +88,14 @@ class TbError(RuntimeError):
 
 
 def _load():
+    # torch ships its own HIP runtime (same soname as ROCm's).  Loading it
+    # first makes libtb.so bind to that one runtime, so that torch streams and
+    # device pointers handed to the library are valid in it; two runtimes in
+    # one process would not see each other's devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             "libtb.so is not built at %s; run `python paper_2112_11991_amd/build.py` (hipcc, gfx950)" % LIB_PATH

@@ -122,9 +122,10 @@ def test_c1_candidates_match_oracle(tb):
     _say("  matched %d, near-threshold exempt %d" % (matched, exempt))
     assert matched > 0
     assert np.allclose(thr, [oracle.threshold(1 << l, 6.0) for l in range(5)], rtol=1e-6)
-    # the injected pulsar is the strongest detection, at its own template
-    best = cg[np.argmax(cg["sigma"])]
-    assert best["template_id"] == 1000 + len(w.templates) - 1
+    # the strongest detection is the oracle's (2^17 samples span 0.1% of the
+    # 2 h orbit, so every template recovers the pulsar about equally well)
+    bg, bo = cg[np.argmax(cg["sigma"])], co[np.argmax(co["sigma"])]
+    assert (bg["template_id"], bg["log2_harm"], bg["bin"]) == (bo["template_id"], bo["log2_harm"], bo["bin"])
 
 
 def test_elliptical_candidates_match_oracle(tb):
