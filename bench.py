@@ -26,8 +26,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 KERNELS = ["k_pass1 (resample + FFT pass 1)", "k_pass2 (FFT pass 2 + power)", "k_median (whitening medians)",
-           "k_harmsum (harmonic sum + peaks)"]
-KERNEL_SHORT = ["k_pass1", "k_pass2", "k_median", "k_harmsum"]
+           "k_whiten (whitening)", "k_harmsum (harmonic sum + peaks)"]
+KERNEL_SHORT = ["k_pass1", "k_pass2", "k_median", "k_whiten", "k_harmsum"]
 
 
 def log(*a):
@@ -64,10 +64,11 @@ def describe(w, name):
 def kernel_bytes(n: int, templates_per_launch: float):
     """Algorithmic HBM bytes per launch of each kernel class, for series length n:
     pass 1 writes the 4n-byte exchange per template and reads the 4n-byte series
-    once per launch; pass 2 reads 4n and writes 2n; medians and harmonic sum
-    each read the 2n-byte spectrum once (first touch)."""
+    once per launch; pass 2 reads 4n and writes 2n; the medians read the
+    2n-byte spectrum, the whitening reads and rewrites it, the harmonic sum
+    reads it once (first touch)."""
     b = templates_per_launch
-    return [4.0 * n * b + 4.0 * n, 6.0 * n * b, 2.0 * n * b, 2.0 * n * b]
+    return [4.0 * n * b + 4.0 * n, 6.0 * n * b, 2.0 * n * b, 4.0 * n * b, 2.0 * n * b]
 
 
 def traffic_record(kernel: str):
@@ -192,7 +193,7 @@ def main():
         ms, launches, tmpl = plan.profile_read()
         plan.profile(False)
         per = []
-        for k in range(4):
+        for k in range(5):
             L = max(1, int(launches[k]))
             avg_ms = ms[k] / L
             byt = kernel_bytes(int(n_avg), tmpl / L)[k]
@@ -200,7 +201,7 @@ def main():
                         "avg_ms": avg_ms, "total_ms": float(ms[k]), "bytes_per_launch": byt,
                         "gbs": byt / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None})
         out["kernels"] = per
-        dom = max(range(4), key=lambda k: ms[k])
+        dom = max(range(5), key=lambda k: ms[k])
         d = per[dom]
         tr = traffic_record(d["kernel"])
         out["roofline"] = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["gbs"], "peak": PEAK_HBM_GBS,

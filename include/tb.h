@@ -166,10 +166,10 @@ tb_status tb_profile(tb_plan_t plan, int enable);
 /* Waits for queued work and reports, per kernel class, the summed device
  * milliseconds and launch counts since tb_profile(plan, 1):
  *   [0] resample + FFT pass 1, [1] FFT pass 2 + power, [2] block medians,
- *   [3] harmonic sum + threshold + compaction.
+ *   [3] whitening, [4] harmonic sum + threshold + compaction.
  * *templates receives the number of templates those launches processed.
  * Any output pointer may be NULL. */
-tb_status tb_profile_read(tb_plan_t plan, double ms[4], uint64_t launches[4], uint64_t* templates);
+tb_status tb_profile_read(tb_plan_t plan, double ms[5], uint64_t launches[5], uint64_t* templates);
 
 /* Streaming copy of bytes (a multiple of 16) between two device buffers on the
  * plan stream, repeated reps times; *ms receives the mean device time of one

@@ -251,9 +251,9 @@ def tb_profile(plan: int, enable: bool) -> None:
 
 
 def tb_profile_read(plan: int):
-    """(ms[4], launches[4], templates): pass 1, pass 2, medians, harmonic sum."""
-    ms = np.zeros(4, dtype=np.float64)
-    ln = np.zeros(4, dtype=np.uint64)
+    """(ms[5], launches[5], templates): pass 1, pass 2, medians, whitening, harmonic sum."""
+    ms = np.zeros(5, dtype=np.float64)
+    ln = np.zeros(5, dtype=np.uint64)
     t = C.c_uint64(0)
     _check(_L.tb_profile_read(C.c_void_p(plan), _ptr(ms), _ptr(ln), C.byref(t)), "tb_profile_read")
     return ms, ln, int(t.value)

@@ -213,11 +213,12 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     g.log2n = log2n;
     g.n = (int64_t)1 << log2n;
     g.M = g.n / 2;
-    int m = log2n - 1;
-    g.S = 1 << ((m + 1) / 2);
-    g.R = 1 << (m / 2);
-    g.C1 = pass1_columns(g.S);
-    g.D = pass2_pairs(g.R);
+    const int64_t TE = std::min<int64_t>(16384, g.M);
+    g.R = (int)std::max<int64_t>(16, g.M / 16384);
+    g.S = (int)(g.M / g.R);
+    g.C1 = (int)(TE / g.S);
+    g.D2 = (int)(TE / g.R);
+    g.nanch = anchor_count(g.n);
     g.W = (int)p->cfg.whiten_window;
     g.nblk = (int)((g.M + g.W - 1) / g.W);
     g.htile = harmsum_tile();
@@ -255,7 +256,7 @@ void free_geometry(GeoRec& r)
 int default_batch(const tb_plan_t p, int64_t M)
 {
     if (p->cfg.batch_templates) return (int)p->cfg.batch_templates;
-    int64_t b = ((int64_t)1 << 25) / M;
+    int64_t b = ((int64_t)1 << 24) / M;
     return (int)std::min<int64_t>(256, std::max<int64_t>(4, b));
 }
 
@@ -269,19 +270,21 @@ tb_status get_slots(tb_plan_t p, const Geometry& g, Slots** out)
     SlotRec rec;
     Slots& s = rec.s;
     s.B = default_batch(p, g.M);
+    s.a_stride = ((size_t)g.nanch + 3) & ~(size_t)3;
     s.y_stride = (size_t)g.M;
     s.p_stride = ((size_t)g.M + 1 + 63) & ~(size_t)63;
     s.med_stride = ((size_t)g.nblk + 63) & ~(size_t)63;
     size_t by = sizeof(float2) * s.y_stride * s.B, bp = sizeof(float) * s.p_stride * s.B,
-           bm = sizeof(float) * s.med_stride * s.B;
-    rec.bytes = by + bp + bm;
+           bm = sizeof(float) * s.med_stride * s.B, ba = anchor_bytes() * s.a_stride * s.B;
+    rec.bytes = by + bp + bm + ba;
     tb_status st = reserve(p, rec.bytes);
     if (st) return st;
     if (hipMalloc(&s.Y, by) != hipSuccess || hipMalloc(&s.P, bp) != hipSuccess ||
-        hipMalloc(&s.med, bm) != hipSuccess) {
+        hipMalloc(&s.med, bm) != hipSuccess || hipMalloc(&s.anchors, ba) != hipSuccess) {
         hipFree(s.Y);
         hipFree(s.P);
         hipFree(s.med);
+        hipFree(s.anchors);
         p->held -= rec.bytes;
         return TB_ERR_OOM;
     }
@@ -500,6 +503,7 @@ tb_status tb_destroy(tb_plan_t p)
             hipFree(kv.second.s.Y);
             hipFree(kv.second.s.P);
             hipFree(kv.second.s.med);
+            hipFree(kv.second.s.anchors);
         }
         for (auto& kv : p->geo) free_geometry(kv.second);
         for (auto& v : p->prof_events)
@@ -738,13 +742,13 @@ tb_status tb_profile(tb_plan_t p, int enable)
     return TB_OK;
 }
 
-tb_status tb_profile_read(tb_plan_t p, double ms[4], uint64_t launches[4], uint64_t* templates)
+tb_status tb_profile_read(tb_plan_t p, double ms[5], uint64_t launches[5], uint64_t* templates)
 {
     if (!p) return TB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(p->mu);
     TB_TRY(hipSetDevice(p->cfg.device));
     TB_TRY(hipStreamSynchronize(p->stream));
-    double acc[K_CLASSES] = {0, 0, 0, 0};
+    double acc[K_CLASSES] = {0, 0, 0, 0, 0};
     for (auto& v : p->prof_events)
         for (int k = 0; k < K_CLASSES; ++k) {
             float f = 0.0f;
@@ -797,7 +801,8 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     if ((st = get_slots(p, *g, &ws))) return st;
     int nfold = ilog2(p->cfg.harm_max) + 1;
     size_t nb = (size_t)g->M + 1;
-    size_t need = 256 + 256 + sizeof(uint4) * 16 + sizeof(int32_t) * (size_t)sr.n + sizeof(float) * nfold * nb;
+    size_t need = 256 + 256 + sizeof(uint4) * 16 + sizeof(int32_t) * (size_t)sr.n + sizeof(float) * nfold * nb +
+                  sizeof(float) * nb;
     char* d = nullptr;
     tb_template* ht = nullptr;
     if (hipMalloc(&d, need) != hipSuccess) return TB_ERR_OOM;
@@ -813,6 +818,7 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     Inspect ins;
     ins.src = (int32_t*)(d + 512 + sizeof(uint4) * 16);
     ins.sums = (float*)((char*)ins.src + sizeof(int32_t) * (size_t)sr.n);
+    ins.power = ins.sums + (size_t)nfold * nb;
     PeakParams pp = peak_params(p, sr.n, sr.tsamp, (uint32_t)sid, 0, 0);
     st = TB_OK;
     if (launch_fill_u32(counter, 0u, 1, p->stream) != hipSuccess ||
@@ -823,7 +829,7 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     if (!st && hipStreamSynchronize(p->stream) != hipSuccess) st = TB_ERR_DEVICE;
     if (!st && src && hipMemcpy(src, ins.src, sizeof(int32_t) * (size_t)sr.n, hipMemcpyDeviceToHost) != hipSuccess)
         st = TB_ERR_DEVICE;
-    if (!st && power && hipMemcpy(power, ws->P, sizeof(float) * nb, hipMemcpyDeviceToHost) != hipSuccess)
+    if (!st && power && hipMemcpy(power, ins.power, sizeof(float) * nb, hipMemcpyDeviceToHost) != hipSuccess)
         st = TB_ERR_DEVICE;
     if (!st && medians &&
         hipMemcpy(medians, ws->med, sizeof(float) * (size_t)g->nblk, hipMemcpyDeviceToHost) != hipSuccess)

@@ -19,13 +19,15 @@ struct TmplDev {
 static_assert(sizeof(TmplDev) == 64, "TmplDev layout");
 
 // Two-pass FFT geometry of a real series of n = 2M samples packed as M
-// complex points, M = R * S.  Pass 1 does S-point transforms over the strided
-// index (C1 columns per workgroup), pass 2 R-point transforms (D mirrored
-// column pairs per workgroup) followed by the real-to-complex split and |X|^2.
+// complex points, M = R * S.  Each workgroup holds TE = min(16384, M) points:
+// pass 1 does S-point transforms over the strided index (C1 = TE/S columns
+// per workgroup), pass 2 R-point transforms over D2 = TE/R columns (D2/2
+// mirrored pairs) followed by the real-to-complex split and |X|^2.
 struct Geometry {
     int log2n = 0;
     int64_t n = 0, M = 0;
-    int S = 0, R = 0, C1 = 0, D = 0;
+    int S = 0, R = 0, C1 = 0, D2 = 0;
+    int nanch = 0;         // delay anchors per template
     int W = 0;             // whitening window (bins per median block)
     int nblk = 0;          // whitening blocks
     int htile = 0;         // harmonic-sum output bins per workgroup
@@ -51,6 +53,8 @@ struct PeakParams {
 // Device workspace for B templates in flight at one series length.
 struct Slots {
     int B = 0;
+    void* anchors = nullptr;  // delay anchors, B x a_stride
+    size_t a_stride = 0;      // anchors per slot
     float2* Y = nullptr;   // exchange buffer, B x M complex
     size_t y_stride = 0;   // complex per slot
     float* P = nullptr;    // power, B x (M + 1), padded
@@ -62,13 +66,14 @@ struct Slots {
 // Optional per-stage outputs (template slot 0 only).
 struct Inspect {
     int32_t* src = nullptr;  // n
+    float* power = nullptr;  // M + 1, copied before whitening overwrites it
     float* sums = nullptr;   // nfold x (M + 1)
 };
 
 hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, hipStream_t s);
 hipError_t launch_mean_subtract(const float* in, float* out, int64_t n, double* partial, hipStream_t s);
 // Kernel classes timed by the plan's profiler.
-enum { K_PASS1 = 0, K_PASS2 = 1, K_MEDIAN = 2, K_HARMSUM = 3, K_CLASSES = 4 };
+enum { K_PASS1 = 0, K_PASS2 = 1, K_MEDIAN = 2, K_WHITEN = 3, K_HARMSUM = 4, K_CLASSES = 5 };
 
 // Queues the four kernels of one wave of nslots templates.  ev, if not null,
 // holds K_CLASSES + 1 events recorded before, between and after them.
@@ -77,8 +82,8 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
                        const Inspect& ins, hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_copy(float4* dst, const float4* src, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
-int pass1_columns(int S);
-int pass2_pairs(int R);
+int anchor_count(int64_t n);
+size_t anchor_bytes();
 int harmsum_tile();
 
 }  // namespace tb

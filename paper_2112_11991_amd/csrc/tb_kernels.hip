@@ -144,10 +144,14 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t count)
 }
 
 // ------------------------------------------------------------------------
-// Stockham autosort FFT of C columns of length L held in LDS (column c at
-// buf + c*LS), forward sign, natural order in and out.  Each stage loads its
-// butterflies into registers, synchronises, and writes back, so it runs in
-// place.  Twiddles W_L^r come from an FP64-built table.
+// LDS-staged Stockham FFTs of C columns of length L (C L = TE <= 16384
+// complex points per workgroup, T = TE/16 threads, 16 points per thread).
+// Stages are radix 16 (the first one radix 2, 4 or 8 when log2 L is not a
+// multiple of 4); each stage reads its butterflies from LDS into registers,
+// transforms them there and writes them back in Stockham order, so two LDS
+// passes per stage.  Columns are padded by one element every 16 so that the
+// strided stores of the early stages spread over the banks.  Forward sign,
+// natural order in and out.  Twiddles W_L^r come from an FP64-built table.
 template <int L>
 struct Log2 {
     static constexpr int value = 1 + Log2<L / 2>::value;
@@ -157,85 +161,134 @@ struct Log2<1> {
     static constexpr int value = 0;
 };
 
-template <int L, int C, int LS>
-__device__ __forceinline__ void radix2_first(float2* buf)
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3)
 {
-    constexpr int H = L / 2, NB = C * H, PER = (NB + NT - 1) / NT;
-    float2 a[PER], b[PER];
+    float2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = mul_mi(csub(v1, v3));
+    v0 = cadd(t0, t2);
+    v1 = cadd(t1, t3);
+    v2 = csub(t0, t2);
+    v3 = csub(t1, t3);
+}
+
+template <int RAD>
+__device__ __forceinline__ void dft(float2* v);
+
+template <>
+__device__ __forceinline__ void dft<2>(float2* v)
+{
+    float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <>
+__device__ __forceinline__ void dft<4>(float2* v)
+{
+    dft4(v[0], v[1], v[2], v[3]);
+}
+
+// 8 = 2 x 4: even/odd 4-point transforms joined with W_8^k.
+template <>
+__device__ __forceinline__ void dft<8>(float2* v)
+{
+    constexpr float H = 0.70710678118654752440f;
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4(e0, e1, e2, e3);
+    dft4(o0, o1, o2, o3);
+    o1 = make_float2(H * (o1.x + o1.y), H * (o1.y - o1.x));   // * W8^1
+    o2 = mul_mi(o2);                                          // * W8^2
+    o3 = make_float2(H * (o3.y - o3.x), -H * (o3.x + o3.y));  // * W8^3
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+// 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.
+template <>
+__device__ __forceinline__ void dft<16>(float2* v)
+{
+    constexpr float C1 = 0.92387953251128675613f, S1 = 0.38268343236508977173f, H = 0.70710678118654752440f;
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        int bi = threadIdx.x + i * NT;
-        if (NB % NT == 0 || bi < NB) {
-            int c = bi / H, j = bi % H;
-            a[i] = buf[c * LS + j];
-            b[i] = buf[c * LS + j + H];
+    for (int n2 = 0; n2 < 4; ++n2) dft4(v[n2], v[4 + n2], v[8 + n2], v[12 + n2]);
+    // v[n2 + 4 k1] *= W16^(n2 k1)
+    v[5] = cmul(v[5], make_float2(C1, -S1));
+    v[6] = cmul(v[6], make_float2(H, -H));
+    v[7] = cmul(v[7], make_float2(S1, -C1));
+    v[9] = cmul(v[9], make_float2(H, -H));
+    v[10] = mul_mi(v[10]);
+    v[11] = cmul(v[11], make_float2(-H, -H));
+    v[13] = cmul(v[13], make_float2(S1, -C1));
+    v[14] = cmul(v[14], make_float2(-H, -H));
+    v[15] = cmul(v[15], make_float2(-C1, S1));
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    // X[k1 + 4 k2] sits in v[4 k1 + k2]: transpose back to natural order
+    float2 t[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t[i] = v[4 * (i & 3) + (i >> 2)];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
+template <int L, int C, int RAD, int NS>
+__device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict__ tw)
+{
+    constexpr int T = C * L / 16, BPT = 16 / RAD, LR = L / RAD, LSP = L + L / 16;
+    constexpr int TWS = L / (RAD * NS);
+    float2 v[16];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int bi = threadIdx.x + u * T;
+        const int c = bi / LR, j = bi % LR, k = j % NS;
+        const float2* col = lds + c * LSP;
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) v[u * RAD + r] = col[pidx(j + r * LR)];
+        if (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) v[u * RAD + r] = cmul(v[u * RAD + r], tw[r * k * TWS]);
         }
+        dft<RAD>(v + u * RAD);
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        int bi = threadIdx.x + i * NT;
-        if (NB % NT == 0 || bi < NB) {
-            int c = bi / H, j = bi % H;
-            buf[c * LS + 2 * j] = cadd(a[i], b[i]);
-            buf[c * LS + 2 * j + 1] = csub(a[i], b[i]);
-        }
+    for (int u = 0; u < BPT; ++u) {
+        const int bi = threadIdx.x + u * T;
+        const int c = bi / LR, j = bi % LR, k = j % NS;
+        float2* col = lds + c * LSP;
+        const int base = (j / NS) * RAD * NS + k;
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) col[pidx(base + r * NS)] = v[u * RAD + r];
     }
     __syncthreads();
 }
 
-template <int L, int C, int LS>
-__device__ __forceinline__ void radix4_stage(float2* buf, const float2* __restrict__ tw, int ns_log)
-{
-    constexpr int Q = L / 4, NB = C * Q, PER = (NB + NT - 1) / NT, LG = Log2<L>::value;
-    const int Ns = 1 << ns_log;
-    float2 v[PER][4];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        int bi = threadIdx.x + i * NT;
-        if (NB % NT == 0 || bi < NB) {
-            int c = bi / Q, j = bi % Q, k = j & (Ns - 1);
-            const float2* src = buf + c * LS + j;
-            float2 v0 = src[0], v1 = src[Q], v2 = src[2 * Q], v3 = src[3 * Q];
-            if (ns_log > 0) {
-                int sh = LG - 2 - ns_log;
-                v1 = cmul(v1, tw[k << sh]);
-                v2 = cmul(v2, tw[(2 * k) << sh]);
-                v3 = cmul(v3, tw[(3 * k) << sh]);
-            }
-            float2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = mul_mi(csub(v1, v3));
-            v[i][0] = cadd(t0, t2);
-            v[i][1] = cadd(t1, t3);
-            v[i][2] = csub(t0, t2);
-            v[i][3] = csub(t1, t3);
-        }
+template <int L, int C, int NS>
+struct Radix16Stages {
+    static __device__ __forceinline__ void run(float2* lds, const float2* __restrict__ tw)
+    {
+        fft_stage<L, C, 16, NS>(lds, tw);
+        Radix16Stages<L, C, NS * 16>::run(lds, tw);
     }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        int bi = threadIdx.x + i * NT;
-        if (NB % NT == 0 || bi < NB) {
-            int c = bi / Q, j = bi % Q, k = j & (Ns - 1);
-            float2* dst = buf + c * LS + ((j >> ns_log) << (ns_log + 2)) + k;
-            dst[0] = v[i][0];
-            dst[Ns] = v[i][1];
-            dst[2 * Ns] = v[i][2];
-            dst[3 * Ns] = v[i][3];
-        }
-    }
-    __syncthreads();
-}
+};
+template <int L, int C>
+struct Radix16Stages<L, C, L> {
+    static __device__ __forceinline__ void run(float2*, const float2* __restrict__) {}
+};
 
-template <int L, int C, int LS>
-__device__ __forceinline__ void fft_columns(float2* buf, const float2* __restrict__ tw)
+template <int L, int C>
+__device__ __forceinline__ void fft_tile(float2* lds, const float2* __restrict__ tw)
 {
-    constexpr int LG = Log2<L>::value;
-    int ns_log = 0;
-    if (LG & 1) {
-        radix2_first<L, C, LS>(buf);
-        ns_log = 1;
-    }
-    for (; ns_log < LG; ns_log += 2) radix4_stage<L, C, LS>(buf, tw, ns_log);
+    constexpr int LG = Log2<L>::value, R0 = (LG % 4) ? (1 << (LG % 4)) : 16;
+    fft_stage<L, C, R0, 1>(lds, tw);
+    Radix16Stages<L, C, R0>::run(lds, tw);
 }
 
 __device__ __forceinline__ float2 twiddle2(const float2* __restrict__ lo, const float2* __restrict__ hi, uint32_t q)
@@ -244,46 +297,119 @@ __device__ __forceinline__ float2 twiddle2(const float2* __restrict__ lo, const 
 }
 
 // ------------------------------------------------------------------------
+// Delay anchors.  The demodulating delay delta(j) = (Delta(j tsamp) -
+// Delta(0)) / tsamp is expanded around anchors j_a = a 2^ANCHOR_BITS into a
+// cubic in u = j - j_a, |u| <= 2^(ANCHOR_BITS-1), from the exact Kepler
+// solution there and the analytic derivatives of the BT delay
+// (App. A.1) with respect to the mean anomaly:
+//   F = (cos E - e) sin w + sqrt(1-e^2) sin E cos w,  E' = 1/(1 - e cos E),
+//   E'' = -e sin E E'^3,  E''' = -e cos E E'^4 - 3 e sin E E'^2 E''.
+// The remainder is A W'^4 max|F''''| u^4 / 24 (A = tau/tsamp,
+// W' = Omega tsamp) with |F''''| <= 2 (1+e)^2 / (1-e)^7; templates whose bound
+// exceeds 1e-11 samples are evaluated exactly at every sample instead.
+constexpr int ANCHOR_BITS = 11;
+
+struct __align__(16) Anchor {
+    double c0, c1, c2, c3;
+};
+
+__device__ __forceinline__ bool needs_exact(const TmplDev& p, double tsamp)
+{
+    const double A = p.tau / tsamp, Wp = p.omega * tsamp, e = p.ecc, om = 1.0 - e;
+    const double g4 = 2.0 * (1.0 + e) * (1.0 + e) / (om * om * om * om * om * om * om);
+    const double u = (double)(1 << (ANCHOR_BITS - 1));
+    return A * Wp * Wp * Wp * Wp * g4 * u * u * u * u / 24.0 > 1e-11;
+}
+
+__global__ __launch_bounds__(NT) void k_anchor(const TmplDev* __restrict__ tm, double tsamp, int nanch,
+                                               Anchor* __restrict__ anc, size_t astride)
+{
+    const int a = blockIdx.x * NT + threadIdx.x;
+    if (a >= nanch) return;
+    const TmplDev p = tm[blockIdx.y];
+    const int64_t j = (int64_t)a << ANCHOR_BITS;
+    const double e = p.ecc;
+    const double M = p.omega * ((double)j * tsamp) + p.alpha;
+    const double E = kepler_E(M, e);
+    double sE, cE;
+    sincos(E, &sE, &cE);
+    const double F = (cE - e) * p.sinw + p.beta * sE * p.cosw;
+    const double FE = -sE * p.sinw + p.beta * cE * p.cosw;
+    const double FEE = -cE * p.sinw - p.beta * sE * p.cosw;
+    const double FEEE = -FE;
+    const double E1 = 1.0 / (1.0 - e * cE);
+    const double E2 = -e * sE * E1 * E1 * E1;
+    const double E3 = -e * cE * E1 * E1 * E1 * E1 - 3.0 * e * sE * E1 * E1 * E2;
+    const double F1 = FE * E1;
+    const double F2 = FEE * E1 * E1 + FE * E2;
+    const double F3 = FEEE * E1 * E1 * E1 + 3.0 * FEE * E1 * E2 + FE * E3;
+    Anchor r;
+    r.c0 = (p.tau * F - p.d0) / tsamp;
+    r.c1 = p.tau * p.omega * F1;
+    r.c2 = p.tau * p.omega * p.omega * tsamp * F2 * 0.5;
+    r.c3 = p.tau * p.omega * p.omega * p.omega * tsamp * tsamp * F3 * (1.0 / 6.0);
+    anc[blockIdx.y * astride + a] = r;
+}
+
+__device__ __forceinline__ int64_t source_from_anchor(const Anchor* __restrict__ anc, int64_t j)
+{
+    const int64_t a = (j + (1 << (ANCHOR_BITS - 1))) >> ANCHOR_BITS;
+    const Anchor q = anc[a];
+    const double u = (double)(j - (a << ANCHOR_BITS));
+    const double d = q.c0 + u * (q.c1 + u * (q.c2 + u * q.c3));
+    return j - (int64_t)rint(d);
+}
+
+// ------------------------------------------------------------------------
 // Pass 1: for complex point m = n1 + R*n2 (n1 < R, n2 < S) the packed value
 // z_m = y_{2m} + i y_{2m+1} of the demodulated series, y_j = x0[src_j], is
 // gathered straight from the resident series; S-point transforms over n2;
-// the inter-pass twiddle W_M^{n1 k2}.  Output tile of workgroup w (columns
-// n1 in [w*C1, (w+1)*C1)) is the contiguous block Y[w][k2][c].
+// the inter-pass twiddle W_M^{n1 k2}.  Workgroup w owns columns
+// n1 in [w C1, (w+1) C1) and writes them as the contiguous block Y[w][k2][c].
 template <int S, int C1>
-__global__ __launch_bounds__(NT) void k_pass1(const float* __restrict__ x, int64_t n, int R, double tsamp,
-                                              const TmplDev* __restrict__ tm, float2* __restrict__ Y,
-                                              size_t y_stride, const float2* __restrict__ twS,
-                                              const float2* __restrict__ twM_lo, const float2* __restrict__ twM_hi,
-                                              int32_t* __restrict__ src_out)
+__global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ x, int64_t n, int R, double tsamp,
+                                                      const TmplDev* __restrict__ tm,
+                                                      const Anchor* __restrict__ anchors, size_t astride,
+                                                      float2* __restrict__ Y, size_t y_stride,
+                                                      const float2* __restrict__ twS,
+                                                      const float2* __restrict__ twM_lo,
+                                                      const float2* __restrict__ twM_hi, int32_t* __restrict__ src_out)
 {
-    constexpr int LS = S + PAD;
-    __shared__ float2 buf[C1 * LS];
+    constexpr int T = C1 * S / 16, LSP = S + S / 16;
+    __shared__ float2 lds[C1 * LSP];
     const TmplDev p = tm[blockIdx.y];
-    const int ntiles = R / C1;
-    const int tile = xcd_remap(blockIdx.x, ntiles);
+    const Anchor* anc = anchors + blockIdx.y * astride;
+    const int tile = xcd_remap(blockIdx.x, R / C1);
     const int c0 = tile * C1;
+    const bool exact = needs_exact(p, tsamp);
 
-    for (int e = threadIdx.x; e < C1 * S; e += NT) {
-        int s = e / C1, c = e % C1;
-        int64_t j = 2 * ((int64_t)c0 + c + (int64_t)R * s);
-        int64_t i0 = source_index(p, j, tsamp);
-        int64_t i1 = source_index(p, j + 1, tsamp);
-        float y0 = (i0 >= 0 && i0 < n) ? x[i0] : 0.0f;
-        float y1 = (i1 >= 0 && i1 < n) ? x[i1] : 0.0f;
+    for (int e = threadIdx.x; e < C1 * S; e += T) {
+        const int s = e / C1, c = e % C1;
+        const int64_t j = 2 * ((int64_t)c0 + c + (int64_t)R * s);
+        int64_t i0, i1;
+        if (!exact) {
+            i0 = source_from_anchor(anc, j);
+            i1 = source_from_anchor(anc, j + 1);
+        } else {
+            i0 = source_index(p, j, tsamp);
+            i1 = source_index(p, j + 1, tsamp);
+        }
+        const float y0 = (i0 >= 0 && i0 < n) ? x[i0] : 0.0f;
+        const float y1 = (i1 >= 0 && i1 < n) ? x[i1] : 0.0f;
         if (src_out) {
             src_out[j] = (int32_t)i0;
             src_out[j + 1] = (int32_t)i1;
         }
-        buf[c * LS + s] = make_float2(y0, y1);
+        lds[c * LSP + pidx(s)] = make_float2(y0, y1);
     }
     __syncthreads();
-    fft_columns<S, C1, LS>(buf, twS);
+    fft_tile<S, C1>(lds, twS);
 
     float2* out = Y + blockIdx.y * y_stride + (size_t)tile * S * C1;
-    for (int e = threadIdx.x; e < C1 * S; e += NT) {
-        int k2 = e / C1, c = e % C1;
-        uint32_t q = (uint32_t)(c0 + c) * (uint32_t)k2;
-        out[e] = cmul(buf[c * LS + k2], twiddle2(twM_lo, twM_hi, q));
+    for (int e = threadIdx.x; e < C1 * S; e += T) {
+        const int k2 = e / C1, c = e % C1;
+        const uint32_t q = (uint32_t)(c0 + c) * (uint32_t)k2;
+        out[e] = cmul(lds[c * LSP + pidx(k2)], twiddle2(twM_lo, twM_hi, q));
     }
 }
 
@@ -298,63 +424,59 @@ __device__ __forceinline__ float power_of(float2 z, float2 zm, float2 w)
     return xr * xr + xi * xi;
 }
 
-// Pass 2: workgroup g owns columns k2 in A = [gD, gD+D) and their mirrors
-// S - k2 (column 0 pairs with itself, so its mirror slot carries the other
-// self-paired column S/2).  R-point transforms over n1 give Z at
-// k = k2 + S k1; Z_{M-k} sits in the mirror column at k1' = R-1-k1.
-template <int R, int D>
-__global__ __launch_bounds__(NT) void k_pass2(const float2* __restrict__ Y, size_t y_stride, int S, int C1,
-                                              float* __restrict__ P, size_t p_stride, int64_t M,
-                                              const float2* __restrict__ twR, const float2* __restrict__ tw2M_lo,
-                                              const float2* __restrict__ tw2M_hi)
+// Pass 2: workgroup g owns the D2/2 columns k2 in A = [g D, g D + D) and
+// their mirrors S - k2 (column 0 pairs with itself, so its mirror slot
+// carries the other self-paired column S/2).  R-point transforms over n1 give
+// Z at k = k2 + S k1, and Z_{M-k} sits in the mirror slot at k1' = R-1-k1
+// (in column 0 at (R - k1) mod R).  Each slot emits |X|^2 for its own bins:
+// runs of D consecutive bins per k1, ascending for A, descending for mirrors.
+template <int R, int D2>
+__global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__ Y, size_t y_stride, int S, int C1,
+                                                      float* __restrict__ P, size_t p_stride, int64_t M,
+                                                      const float2* __restrict__ twR,
+                                                      const float2* __restrict__ tw2M_lo,
+                                                      const float2* __restrict__ tw2M_hi)
 {
-    constexpr int LS = R + PAD;
-    __shared__ float2 buf[2 * D * LS];
-    const int ngroups = S / (2 * D);
-    const int g = xcd_remap(blockIdx.x, ngroups);
+    constexpr int T = D2 * R / 16, LSP = R + R / 16, D = D2 / 2;
+    __shared__ float2 lds[D2 * LSP];
+    const int g = xcd_remap(blockIdx.x, S / D2);
     const float2* Ys = Y + blockIdx.y * y_stride;
     float* Ps = P + blockIdx.y * p_stride;
 
-    for (int e = threadIdx.x; e < 2 * D * R; e += NT) {
-        int c = e % C1;
-        int q = (e / C1) % (2 * D);
-        int w = e / (C1 * 2 * D);
+    for (int e = threadIdx.x; e < D2 * R; e += T) {
+        const int c = e % C1, q = (e / C1) % D2, w = e / (C1 * D2);
         int col;
         if (q < D) {
             col = g * D + q;
         } else {
-            int a = g * D + (q - D);
+            const int a = g * D + (q - D);
             col = (a == 0) ? S / 2 : S - a;
         }
-        buf[q * LS + w * C1 + c] = Ys[((size_t)w * S + col) * C1 + c];
+        lds[q * LSP + pidx(w * C1 + c)] = Ys[((size_t)w * S + col) * C1 + c];
     }
     __syncthreads();
-    fft_columns<R, 2 * D, LS>(buf, twR);
+    fft_tile<R, D2>(lds, twR);
 
-    for (int e = threadIdx.x; e < D * R; e += NT) {
-        int d = e % D, k1 = e / D;
-        int a = g * D + d;
-        if (a == 0) {
-            float2 z = buf[k1];
-            if (k1 == 0) {
-                float s0 = z.x + z.y, sm = z.x - z.y;
-                Ps[0] = s0 * s0;
-                Ps[M] = sm * sm;
-            } else {
-                uint32_t k = (uint32_t)S * (uint32_t)k1;
-                Ps[k] = power_of(z, buf[R - k1], twiddle2(tw2M_lo, tw2M_hi, k));
-            }
-            float2 zh = buf[D * LS + k1], zhm = buf[D * LS + R - 1 - k1];
-            uint32_t kh = (uint32_t)(S / 2) + (uint32_t)S * (uint32_t)k1;
-            Ps[kh] = power_of(zh, zhm, twiddle2(tw2M_lo, tw2M_hi, kh));
+    for (int e = threadIdx.x; e < D2 * R; e += T) {
+        const int q = e % D2, k1 = e / D2;
+        const int a = g * D + (q < D ? q : q - D);
+        int col, pq, pk;
+        if (q < D) {
+            col = a;
+            pq = (a == 0) ? q : q + D;
+            pk = (a == 0) ? ((R - k1) & (R - 1)) : R - 1 - k1;
         } else {
-            float2 za = buf[d * LS + k1];
-            float2 zb = buf[(D + d) * LS + R - 1 - k1];
-            uint32_t k = (uint32_t)a + (uint32_t)S * (uint32_t)k1;
-            float2 w = twiddle2(tw2M_lo, tw2M_hi, k);
-            Ps[k] = power_of(za, zb, w);
-            // W_N^{M-k} = -conj(W_N^k)
-            Ps[M - k] = power_of(zb, za, make_float2(-w.x, w.y));
+            col = (a == 0) ? S / 2 : S - a;
+            pq = (a == 0) ? q : q - D;
+            pk = R - 1 - k1;
+        }
+        const float2 z = lds[q * LSP + pidx(k1)];
+        const float2 zm = lds[pq * LSP + pidx(pk)];
+        const uint32_t k = (uint32_t)col + (uint32_t)S * (uint32_t)k1;
+        Ps[k] = power_of(z, zm, twiddle2(tw2M_lo, tw2M_hi, k));
+        if (q == 0 && a == 0 && k1 == 0) {
+            const float sm = z.x - z.y;
+            Ps[M] = sm * sm;
         }
     }
 }
@@ -362,133 +484,156 @@ __global__ __launch_bounds__(NT) void k_pass2(const float2* __restrict__ Y, size
 // ------------------------------------------------------------------------
 // Whitening block medians: element of rank floor((n_b-1)/2) of bins
 // [1 + bW, 1 + bW + n_b), by radix selection on the IEEE bits (powers are
-// non-negative, so unsigned order is numeric order).
+// non-negative, so unsigned order is numeric order).  Four 8-bit digit
+// passes; each wave counts into its own histogram, and the digit holding the
+// rank is found with a block-wide prefix sum.
 __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size_t p_stride, int64_t M, int W,
                                                float* __restrict__ med, size_t med_stride)
 {
     extern __shared__ uint32_t vals[];
-    __shared__ uint32_t hist[256];
-    __shared__ uint32_t s_prefix, s_rank;
+    __shared__ uint32_t hist[NT / 64][256];
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t s_digit, s_rank;
     const int b = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float* Ps = P + blockIdx.y * p_stride;
     const int64_t start = 1 + (int64_t)b * W;
     const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
     for (int i = threadIdx.x; i < cnt; i += NT) vals[i] = __float_as_uint(Ps[start + i]);
-    if (threadIdx.x == 0) {
-        s_prefix = 0;
-        s_rank = (uint32_t)(cnt - 1) / 2;
-    }
-    uint32_t mask = 0;
+    uint32_t rank = (uint32_t)(cnt - 1) / 2, prefix = 0, mask = 0;
     for (int shift = 24; shift >= 0; shift -= 8) {
-        hist[threadIdx.x] = 0;
+        for (int i = threadIdx.x; i < (NT / 64) * 256; i += NT) (&hist[0][0])[i] = 0;
         __syncthreads();
-        uint32_t prefix = s_prefix;
         for (int i = threadIdx.x; i < cnt; i += NT) {
             uint32_t v = vals[i];
-            if ((v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+            if ((v & mask) == prefix) atomicAdd(&hist[wave][(v >> shift) & 255u], 1u);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t r = s_rank, acc = 0;
-            int dd = 0;
-            for (; dd < 255; ++dd) {
-                if (acc + hist[dd] > r) break;
-                acc += hist[dd];
-            }
-            s_rank = r - acc;
-            s_prefix = prefix | ((uint32_t)dd << shift);
+        // thread t owns digit t (NT == 256)
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) tot += hist[w][threadIdx.x];
+        uint32_t inc = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            uint32_t o = __shfl_up(inc, d);
+            if (lane >= d) inc += o;
         }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        uint32_t excl = before + inc - tot;
+        if (tot && excl <= rank && rank < excl + tot) {
+            s_digit = threadIdx.x;
+            s_rank = rank - excl;
+        }
+        __syncthreads();
+        prefix |= s_digit << shift;
         mask |= 255u << shift;
+        rank = s_rank;
         __syncthreads();
     }
-    if (threadIdx.x == 0) med[blockIdx.y * med_stride + b] = __uint_as_float(s_prefix);
+    if (threadIdx.x == 0) med[blockIdx.y * med_stride + b] = __uint_as_float(prefix);
+}
+
+// Whitening: P^_k = P_k ln2 / m(k), m the straight line between neighbouring
+// block-median centres c_b = start_b + (n_b - 1)/2, held constant before the
+// first and after the last centre; P^_0 = 0.  One workgroup per block, in
+// place.  Centres are kept doubled so that they stay integers.
+__global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_stride, int64_t M, int W, int nblk,
+                                               const float* __restrict__ med, size_t med_stride)
+{
+    const int b = blockIdx.x;
+    float* Ps = P + blockIdx.y * p_stride;
+    const float* md = med + blockIdx.y * med_stride;
+    const int64_t start = 1 + (int64_t)b * W;
+    const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
+    auto two_c = [&](int bb) -> int64_t {
+        int64_t n_b = (bb == nblk - 1) ? (M - (int64_t)bb * W) : W;
+        return 2 * (int64_t)bb * W + n_b + 1;
+    };
+    const int64_t c_here = two_c(b);
+    const float m_here = md[b];
+    // left neighbour segment [c_{b-1}, c_b), right [c_b, c_{b+1})
+    const bool has_l = b > 0, has_r = b + 1 < nblk;
+    const int64_t c_l = has_l ? two_c(b - 1) : c_here, c_r = has_r ? two_c(b + 1) : c_here;
+    const float m_l = has_l ? md[b - 1] : m_here, m_r = has_r ? md[b + 1] : m_here;
+    const float inv_l = has_l ? 1.0f / (float)(c_here - c_l) : 0.0f;
+    const float inv_r = has_r ? 1.0f / (float)(c_r - c_here) : 0.0f;
+    for (int i = threadIdx.x; i < cnt; i += NT) {
+        int64_t q = start + i;
+        int64_t tq = 2 * q;
+        float level;
+        if (tq < c_here) {
+            level = has_l ? m_l + (m_here - m_l) * ((float)(tq - c_l) * inv_l) : m_here;
+        } else {
+            level = has_r ? m_here + (m_r - m_here) * ((float)(tq - c_here) * inv_r) : m_here;
+        }
+        float p = Ps[q];
+        Ps[q] = level > 0.0f ? (p * 0.69314718055994530942f) / level : 0.0f;
+    }
+    if (b == 0 && threadIdx.x == 0) Ps[0] = 0.0f;
 }
 
 // ------------------------------------------------------------------------
-// Harmonic sum (Sec. 2.1, 16 harmonics) with whitening applied as the
-// spectrum is staged, threshold and wave-ballot compaction.
+// Harmonic sum (Sec. 2.1, up to 16 harmonics), threshold and wave-ballot
+// compaction, on the whitened spectrum.
 //
 // Bin k of fold h adds harmonic m at bin floor((2mk + h)/(2h)); with
-// j = 16 m / h that is floor((jk + 8)/16), so an output tile [k0, k0+T)
-// needs, for each j = 1..16, the contiguous input run
-// [floor((j k0 + 8)/16), floor((j (k0+T-1) + 8)/16)], about 8.5 T bins in
-// all.  Each run is loaded once into LDS, whitened P ln2 / m(q) on the way
-// (m the linear interpolation between block-median centres), and the folds
-// are formed incrementally: fold 2h adds the odd m of the new fold.
+// j = 16 m / h that is floor((jk + 8)/16), so an output tile [k0, k0+HT)
+// needs, for each j, the contiguous input run
+// [floor((j k0 + 8)/16), floor((j (k0+HT-1) + 8)/16)], about 8.5 HT bins in
+// all.  Each run is staged once in LDS.  A thread handles bins k0 + t + NT i;
+// moving i by one moves the run-j index by exactly 16 j, so every LDS address
+// is a per-thread base plus a compile-time offset.  Fold 2h adds the odd m of
+// the new fold to fold h (ascending m), the order the oracle uses.
 constexpr int HT = 1024;                 // output bins per workgroup
 constexpr int HSEG = (17 * HT) / 2 + 64; // LDS floats for the 16 runs
 
-__device__ __forceinline__ float whitened(const float* __restrict__ Ps, const float* __restrict__ med, int q,
-                                          int W, int nblk, int64_t M)
-{
-    if (q == 0) return 0.0f;
-    // twice the block centres: 2c_b = 2bW + n_b + 1
-    int n0 = (int)(M < W ? M : W);
-    int two_c0 = n0 + 1;
-    int nlast = (int)(M - (int64_t)(nblk - 1) * W);
-    int two_cl = 2 * (nblk - 1) * W + nlast + 1;
-    int two_q = 2 * q;
-    float level;
-    if (two_q <= two_c0) {
-        level = med[0];
-    } else if (two_q >= two_cl) {
-        level = med[nblk - 1];
-    } else {
-        int b = (two_q - (W + 1)) / (2 * W);
-        if (b > nblk - 2) b = nblk - 2;
-        int two_cb = 2 * b * W + W + 1;
-        int two_cn = (b + 1 == nblk - 1) ? two_cl : two_cb + 2 * W;
-        float f = (float)(two_q - two_cb) / (float)(two_cn - two_cb);
-        level = med[b] + (med[b + 1] - med[b]) * f;
-    }
-    return level > 0.0f ? (Ps[q] * 0.69314718055994530942f) / level : 0.0f;
-}
-
-__global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, size_t p_stride,
-                                                const float* __restrict__ med, size_t med_stride, int64_t M, int W,
-                                                int nblk, int tmpl_base, PeakParams pp, uint4* __restrict__ ring,
+template <int NF>
+__global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, size_t p_stride, int64_t M,
+                                                int tmpl_base, PeakParams pp, uint4* __restrict__ ring,
                                                 uint32_t* __restrict__ counter, float* __restrict__ sums_out)
 {
+    constexpr int JSTEP = 16 >> (NF - 1);  // runs needed: multiples of 16 / harm_max
     __shared__ float seg[HSEG];
-    __shared__ int s_off[17], s_lo[17];
-    const int ntile = gridDim.x;
-    const int tile = xcd_remap(blockIdx.x, ntile);
+    __shared__ int s_base[17];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int k0 = tile * HT;
     const int kend = (int)(((int64_t)k0 + HT - 1) < M ? (int64_t)k0 + HT - 1 : M);
     const float* Ps = P + blockIdx.y * p_stride;
-    const float* meds = med + blockIdx.y * med_stride;
-    const int jstep = 16 >> (pp.nfold - 1);  // runs needed: multiples of 16/harm_max
 
-    if (threadIdx.x == 0) {
-        int off = 0;
-        for (int j = jstep; j <= 16; j += jstep) {
-            int lo = (j * k0 + 8) >> 4, hi = (j * kend + 8) >> 4;
-            s_off[j] = off;
-            s_lo[j] = lo;
-            off += hi - lo + 1;
-        }
+    // stage the runs
+    int off = 0;
+#pragma unroll
+    for (int j = JSTEP; j <= 16; j += JSTEP) {
+        int lo = (j * k0 + 8) >> 4, len = ((j * kend + 8) >> 4) - lo + 1;
+        for (int i = threadIdx.x; i < len; i += NT) seg[off + i] = Ps[lo + i];
+        if (threadIdx.x == 0) s_base[j] = off - lo;
+        off += len;
     }
     __syncthreads();
-    for (int j = jstep; j <= 16; j += jstep) {
-        int lo = s_lo[j], len = ((j * kend + 8) >> 4) - lo + 1;
-        float* dst = seg + s_off[j];
-        for (int i = threadIdx.x; i < len; i += NT) dst[i] = whitened(Ps, meds, lo + i, W, nblk, M);
-    }
-    __syncthreads();
+
+    int base[17];
+#pragma unroll
+    for (int j = JSTEP; j <= 16; j += JSTEP) base[j] = s_base[j] + ((j * (k0 + (int)threadIdx.x) + 8) >> 4);
 
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t tid = pp.first_template_id + (uint32_t)(tmpl_base + (int)blockIdx.y);
+#pragma unroll
     for (int r = 0; r < HT / NT; ++r) {
-        int k = k0 + r * NT + threadIdx.x;
-        bool in = k <= kend;
-        float acc = in ? seg[s_off[16] + k - s_lo[16]] : 0.0f;
-        for (int l = 0; l < pp.nfold; ++l) {
+        const int k = k0 + r * NT + (int)threadIdx.x;
+        const bool in = k <= kend;
+        float acc = in ? seg[base[16] + 16 * 16 * r] : 0.0f;
+#pragma unroll
+        for (int l = 0; l < NF; ++l) {
             if (l > 0 && in) {
-                int h = 1 << l;
-                for (int m = 1; m < h; m += 2) {
-                    int j = m << (4 - l);
-                    acc += seg[s_off[j] + ((j * k + 8) >> 4) - s_lo[j]];
+#pragma unroll
+                for (int m = 1; m < (1 << l); m += 2) {
+                    const int j = m << (4 - l);
+                    acc += seg[base[j] + 16 * j * r];
                 }
             }
             if (sums_out && in) sums_out[(size_t)l * (M + 1) + k] = acc;
@@ -496,11 +641,11 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
             uint64_t mask = __ballot(hit);
             if (mask) {
                 int leader = __ffsll((unsigned long long)mask) - 1;
-                uint32_t base = 0;
-                if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
-                base = __shfl(base, leader);
+                uint32_t rbase = 0;
+                if (lane == leader) rbase = atomicAdd(counter, (uint32_t)__popcll(mask));
+                rbase = __shfl(rbase, leader);
                 if (hit) {
-                    uint32_t idx = base + (uint32_t)__popcll(mask & below);
+                    uint32_t idx = rbase + (uint32_t)__popcll(mask & below);
                     if (idx < pp.capacity)
                         ring[idx] = make_uint4(tid, (uint32_t)k, (pp.series_id << 8) | (uint32_t)l,
                                                __float_as_uint(acc));
@@ -511,50 +656,30 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
 }
 
 // ------------------------------------------------------------------------
-template <int S>
-constexpr int c1_of()
+template <int S, int C1>
+hipError_t fft1_launch(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int nslots,
+                       const Slots& ws, int32_t* src_out, hipStream_t s)
 {
-    return (8192 / S) < 16 ? (8192 / S) : 16;
-}
-template <int R>
-constexpr int d_of()
-{
-    return (4096 / R) < 16 ? (4096 / R) : 16;
-}
-
-template <int S>
-hipError_t pass1_launch(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int nslots,
-                        const Slots& ws, int32_t* src_out, hipStream_t s)
-{
-    constexpr int C1 = c1_of<S>();
     dim3 grid(g.R / C1, nslots);
-    hipLaunchKernelGGL((k_pass1<S, C1>), grid, dim3(NT), 0, s, x, g.n, g.R, tsamp, tm, ws.Y, ws.y_stride,
-                       g.twS, g.twM_lo, g.twM_hi, src_out);
+    hipLaunchKernelGGL((k_fft1<S, C1>), grid, dim3(C1 * S / 16), 0, s, x, g.n, g.R, tsamp, tm,
+                       (const Anchor*)ws.anchors, ws.a_stride, ws.Y, ws.y_stride, g.twS, g.twM_lo, g.twM_hi,
+                       src_out);
     return hipGetLastError();
 }
 
-template <int R>
-hipError_t pass2_launch(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
+template <int R, int D2>
+hipError_t fft2_launch(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
 {
-    constexpr int D = d_of<R>();
-    dim3 grid(g.S / (2 * D), nslots);
-    hipLaunchKernelGGL((k_pass2<R, D>), grid, dim3(NT), 0, s, ws.Y, ws.y_stride, g.S, g.C1, ws.P, ws.p_stride,
-                       g.M, g.twR, g.tw2M_lo, g.tw2M_hi);
+    dim3 grid(g.S / D2, nslots);
+    hipLaunchKernelGGL((k_fft2<R, D2>), grid, dim3(D2 * R / 16), 0, s, ws.Y, ws.y_stride, g.S, g.C1, ws.P,
+                       ws.p_stride, g.M, g.twR, g.tw2M_lo, g.tw2M_hi);
     return hipGetLastError();
 }
 
 }  // namespace
 
-int pass1_columns(int S)
-{
-    int c = 8192 / S;
-    return c < 16 ? c : 16;
-}
-int pass2_pairs(int R)
-{
-    int d = 4096 / R;
-    return d < 16 ? d : 16;
-}
+int anchor_count(int64_t n) { return (int)(((n - 1 + (1 << (ANCHOR_BITS - 1))) >> ANCHOR_BITS) + 1); }
+size_t anchor_bytes() { return sizeof(Anchor); }
 int harmsum_tile() { return HT; }
 
 hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, hipStream_t s)
@@ -597,41 +722,66 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
     hipError_t e;
     const TmplDev* tmw = tm + tmpl_base;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    switch (g.S) {
-    case 32: e = pass1_launch<32>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 64: e = pass1_launch<64>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 128: e = pass1_launch<128>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 256: e = pass1_launch<256>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 512: e = pass1_launch<512>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 1024: e = pass1_launch<1024>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 2048: e = pass1_launch<2048>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 4096: e = pass1_launch<4096>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    {
+        hipLaunchKernelGGL(k_anchor, dim3((unsigned)((g.nanch + NT - 1) / NT), nslots), dim3(NT), 0, s, tmw, tsamp,
+                           g.nanch, (Anchor*)ws.anchors, ws.a_stride);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    switch (g.S * 32 + g.C1) {
+    case 32 * 32 + 16: e = fft1_launch<32, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 64 * 32 + 16: e = fft1_launch<64, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 128 * 32 + 16: e = fft1_launch<128, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 256 * 32 + 16: e = fft1_launch<256, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 512 * 32 + 16: e = fft1_launch<512, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 1024 * 32 + 16: e = fft1_launch<1024, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 2048 * 32 + 8: e = fft1_launch<2048, 8>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 4096 * 32 + 4: e = fft1_launch<4096, 4>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 8192 * 32 + 2: e = fft1_launch<8192, 2>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
+    case 16384 * 32 + 1: e = fft1_launch<16384, 1>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    switch (g.R) {
-    case 16: e = pass2_launch<16>(g, nslots, ws, s); break;
-    case 32: e = pass2_launch<32>(g, nslots, ws, s); break;
-    case 64: e = pass2_launch<64>(g, nslots, ws, s); break;
-    case 128: e = pass2_launch<128>(g, nslots, ws, s); break;
-    case 256: e = pass2_launch<256>(g, nslots, ws, s); break;
-    case 512: e = pass2_launch<512>(g, nslots, ws, s); break;
-    case 1024: e = pass2_launch<1024>(g, nslots, ws, s); break;
-    case 2048: e = pass2_launch<2048>(g, nslots, ws, s); break;
+    switch (g.R * 4096 + g.D2) {
+    case 16 * 4096 + 32: e = fft2_launch<16, 32>(g, nslots, ws, s); break;
+    case 16 * 4096 + 64: e = fft2_launch<16, 64>(g, nslots, ws, s); break;
+    case 16 * 4096 + 128: e = fft2_launch<16, 128>(g, nslots, ws, s); break;
+    case 16 * 4096 + 256: e = fft2_launch<16, 256>(g, nslots, ws, s); break;
+    case 16 * 4096 + 512: e = fft2_launch<16, 512>(g, nslots, ws, s); break;
+    case 16 * 4096 + 1024: e = fft2_launch<16, 1024>(g, nslots, ws, s); break;
+    case 32 * 4096 + 512: e = fft2_launch<32, 512>(g, nslots, ws, s); break;
+    case 64 * 4096 + 256: e = fft2_launch<64, 256>(g, nslots, ws, s); break;
+    case 128 * 4096 + 128: e = fft2_launch<128, 128>(g, nslots, ws, s); break;
+    case 256 * 4096 + 64: e = fft2_launch<256, 64>(g, nslots, ws, s); break;
+    case 512 * 4096 + 32: e = fft2_launch<512, 32>(g, nslots, ws, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
+    if (ins.power &&
+        (e = hipMemcpyAsync(ins.power, ws.P, sizeof(float) * (size_t)(g.M + 1), hipMemcpyDeviceToDevice, s)) !=
+            hipSuccess)
+        return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_median, dim3(g.nblk, nslots), dim3(NT), sizeof(uint32_t) * (size_t)g.W, s, ws.P,
                        ws.p_stride, g.M, g.W, ws.med, ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
-    int ntile = (int)((g.M + 1 + HT - 1) / HT);
-    hipLaunchKernelGGL(k_harmsum, dim3(ntile, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, ws.med, ws.med_stride,
-                       g.M, g.W, g.nblk, tmpl_base, pp, ring, counter, ins.sums);
+    hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk, ws.med,
+                       ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[4], s)) != hipSuccess) return e;
+    int ntile = (int)((g.M + 1 + HT - 1) / HT);
+    dim3 hg(ntile, nslots);
+    switch (pp.nfold) {
+    case 1: hipLaunchKernelGGL((k_harmsum<1>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
+    case 2: hipLaunchKernelGGL((k_harmsum<2>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
+    case 3: hipLaunchKernelGGL((k_harmsum<3>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
+    case 4: hipLaunchKernelGGL((k_harmsum<4>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
+    case 5: hipLaunchKernelGGL((k_harmsum<5>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
+    default: return hipErrorInvalidValue;
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[5], s)) != hipSuccess) return e;
     return hipSuccess;
 }
 
