@@ -217,8 +217,8 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     g.R = (int)std::max<int64_t>(16, g.M / 16384);
     g.S = (int)(g.M / g.R);
     g.C1 = (int)(TE / g.S);
+    g.lgR = ilog2((uint64_t)g.R);
     g.D2 = (int)(TE / g.R);
-    g.nanch = anchor_count(g.n);
     g.W = (int)p->cfg.whiten_window;
     g.nblk = (int)((g.M + g.W - 1) / g.W);
     g.htile = harmsum_tile();
@@ -270,21 +270,19 @@ tb_status get_slots(tb_plan_t p, const Geometry& g, Slots** out)
     SlotRec rec;
     Slots& s = rec.s;
     s.B = default_batch(p, g.M);
-    s.a_stride = ((size_t)g.nanch + 3) & ~(size_t)3;
     s.y_stride = (size_t)g.M;
     s.p_stride = ((size_t)g.M + 1 + 63) & ~(size_t)63;
     s.med_stride = ((size_t)g.nblk + 63) & ~(size_t)63;
     size_t by = sizeof(float2) * s.y_stride * s.B, bp = sizeof(float) * s.p_stride * s.B,
-           bm = sizeof(float) * s.med_stride * s.B, ba = anchor_bytes() * s.a_stride * s.B;
-    rec.bytes = by + bp + bm + ba;
+           bm = sizeof(float) * s.med_stride * s.B;
+    rec.bytes = by + bp + bm;
     tb_status st = reserve(p, rec.bytes);
     if (st) return st;
     if (hipMalloc(&s.Y, by) != hipSuccess || hipMalloc(&s.P, bp) != hipSuccess ||
-        hipMalloc(&s.med, bm) != hipSuccess || hipMalloc(&s.anchors, ba) != hipSuccess) {
+        hipMalloc(&s.med, bm) != hipSuccess) {
         hipFree(s.Y);
         hipFree(s.P);
         hipFree(s.med);
-        hipFree(s.anchors);
         p->held -= rec.bytes;
         return TB_ERR_OOM;
     }
@@ -503,7 +501,6 @@ tb_status tb_destroy(tb_plan_t p)
             hipFree(kv.second.s.Y);
             hipFree(kv.second.s.P);
             hipFree(kv.second.s.med);
-            hipFree(kv.second.s.anchors);
         }
         for (auto& kv : p->geo) free_geometry(kv.second);
         for (auto& v : p->prof_events)
@@ -534,19 +531,28 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
         p->held -= r.bytes;
         return TB_ERR_OOM;
     }
-    const float* src = data;
+    Geometry* g = nullptr;
+    tb_status gst = get_geometry(p, ilog2(n), &g);
+    if (gst) {
+        hipFree(r.d);
+        p->held -= r.bytes;
+        return gst;
+    }
+    // staging: [0, n) raw copy (host input), [n, 2n) mean-removed natural order
     float* staging = nullptr;
+    if (hipMalloc(&staging, 2 * r.bytes) != hipSuccess) {
+        hipFree(r.d);
+        p->held -= r.bytes;
+        return TB_ERR_OOM;
+    }
+    const float* src = data;
+    hipError_t e = hipSuccess;
     if (flags == TB_MEM_HOST) {
-        if (hipMalloc(&staging, r.bytes) != hipSuccess ||
-            hipMemcpyAsync(staging, data, r.bytes, hipMemcpyHostToDevice, p->stream) != hipSuccess) {
-            hipFree(staging);
-            hipFree(r.d);
-            p->held -= r.bytes;
-            return TB_ERR_DEVICE;
-        }
+        e = hipMemcpyAsync(staging, data, r.bytes, hipMemcpyHostToDevice, p->stream);
         src = staging;
     }
-    hipError_t e = launch_mean_subtract(src, r.d, r.n, p->d_partial, p->stream);
+    if (e == hipSuccess) e = launch_mean_subtract(src, staging + n, r.n, p->d_partial, p->stream);
+    if (e == hipSuccess) e = launch_tile_series(*g, staging + n, r.d, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     hipFree(staging);
     if (e != hipSuccess) {

@@ -26,8 +26,7 @@ static_assert(sizeof(TmplDev) == 64, "TmplDev layout");
 struct Geometry {
     int log2n = 0;
     int64_t n = 0, M = 0;
-    int S = 0, R = 0, C1 = 0, D2 = 0;
-    int nanch = 0;         // delay anchors per template
+    int S = 0, R = 0, C1 = 0, D2 = 0, lgR = 0;
     int W = 0;             // whitening window (bins per median block)
     int nblk = 0;          // whitening blocks
     int htile = 0;         // harmonic-sum output bins per workgroup
@@ -53,8 +52,6 @@ struct PeakParams {
 // Device workspace for B templates in flight at one series length.
 struct Slots {
     int B = 0;
-    void* anchors = nullptr;  // delay anchors, B x a_stride
-    size_t a_stride = 0;      // anchors per slot
     float2* Y = nullptr;   // exchange buffer, B x M complex
     size_t y_stride = 0;   // complex per slot
     float* P = nullptr;    // power, B x (M + 1), padded
@@ -82,8 +79,8 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
                        const Inspect& ins, hipStream_t s, hipEvent_t* ev = nullptr);
 hipError_t launch_copy(float4* dst, const float4* src, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
-int anchor_count(int64_t n);
-size_t anchor_bytes();
+// Rewrites a mean-removed series into the tile order pass 1 reads.
+hipError_t launch_tile_series(const Geometry& g, const float* in, float* out, hipStream_t s);
 int harmsum_tile();
 
 }  // namespace tb

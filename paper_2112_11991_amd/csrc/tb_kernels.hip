@@ -241,7 +241,7 @@ __device__ __forceinline__ void dft<16>(float2* v)
 template <int L, int C, int RAD, int NS>
 __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict__ tw)
 {
-    constexpr int T = C * L / 16, BPT = 16 / RAD, LR = L / RAD, LSP = L + L / 16;
+    constexpr int T = C * L / 16, BPT = 16 / RAD, LR = L / RAD, LSP = L + L / 16 + 1;
     constexpr int TWS = L / (RAD * NS);
     float2 v[16];
 #pragma unroll
@@ -297,67 +297,91 @@ __device__ __forceinline__ float2 twiddle2(const float2* __restrict__ lo, const 
 }
 
 // ------------------------------------------------------------------------
-// Delay anchors.  The demodulating delay delta(j) = (Delta(j tsamp) -
-// Delta(0)) / tsamp is expanded around anchors j_a = a 2^ANCHOR_BITS into a
-// cubic in u = j - j_a, |u| <= 2^(ANCHOR_BITS-1), from the exact Kepler
-// solution there and the analytic derivatives of the BT delay
-// (App. A.1) with respect to the mean anomaly:
-//   F = (cos E - e) sin w + sqrt(1-e^2) sin E cos w,  E' = 1/(1 - e cos E),
-//   E'' = -e sin E E'^3,  E''' = -e cos E E'^4 - 3 e sin E E'^2 E''.
-// The remainder is A W'^4 max|F''''| u^4 / 24 (A = tau/tsamp,
-// W' = Omega tsamp) with |F''''| <= 2 (1+e)^2 / (1-e)^7; templates whose bound
-// exceeds 1e-11 samples are evaluated exactly at every sample instead.
-constexpr int ANCHOR_BITS = 11;
-
-struct __align__(16) Anchor {
-    double c0, c1, c2, c3;
+// Local delay expansion.  A thread's 16 consecutive points of a pass-1 tile
+// cover a short run of sample indices; around its midpoint j_c the delay
+// delta(j) = (Delta(j tsamp) - Delta(0)) / tsamp is expanded to fourth order
+// in u = j - j_c from the exact Kepler solution there and the analytic
+// derivatives of the BT delay (App. A.1) with respect to the mean anomaly
+// (Faa di Bruno, q = E' = 1/(1 - e cos E)):
+//   E'' = -e sE q^3,  E''' = -e cE q^4 + 3 e^2 sE^2 q^5,
+//   E'''' = e sE q^5 + 10 e^2 sE cE q^6 - 15 e^3 sE^3 q^7.
+// The remainder is at most A W'^5 g5(e) U^5 / 120 samples (A = tau/tsamp,
+// W' = Omega tsamp, U the largest |u|, |F^(5)| <= g5 = 3 (1+e)^2/(1-e)^9);
+// when that exceeds 1e-11 the delay is solved exactly at every sample.
+struct DelayPoly {
+    double c0, c1, c2, c3, c4;
 };
 
-__device__ __forceinline__ bool needs_exact(const TmplDev& p, double tsamp)
+__device__ __forceinline__ bool poly_ok(const TmplDev& p, double tsamp, double U)
 {
     const double A = p.tau / tsamp, Wp = p.omega * tsamp, e = p.ecc, om = 1.0 - e;
-    const double g4 = 2.0 * (1.0 + e) * (1.0 + e) / (om * om * om * om * om * om * om);
-    const double u = (double)(1 << (ANCHOR_BITS - 1));
-    return A * Wp * Wp * Wp * Wp * g4 * u * u * u * u / 24.0 > 1e-11;
+    const double om3 = om * om * om;
+    const double g5 = 3.0 * (1.0 + e) * (1.0 + e) / (om3 * om3 * om3);
+    const double w5 = Wp * Wp * Wp * Wp * Wp, u5 = U * U * U * U * U;
+    return A * w5 * g5 * u5 / 120.0 <= 1e-11;
 }
 
-__global__ __launch_bounds__(NT) void k_anchor(const TmplDev* __restrict__ tm, double tsamp, int nanch,
-                                               Anchor* __restrict__ anc, size_t astride)
+__device__ __forceinline__ DelayPoly delay_poly(const TmplDev& p, double tsamp, int64_t jc)
 {
-    const int a = blockIdx.x * NT + threadIdx.x;
-    if (a >= nanch) return;
-    const TmplDev p = tm[blockIdx.y];
-    const int64_t j = (int64_t)a << ANCHOR_BITS;
     const double e = p.ecc;
-    const double M = p.omega * ((double)j * tsamp) + p.alpha;
+    const double M = p.omega * ((double)jc * tsamp) + p.alpha;
     const double E = kepler_E(M, e);
     double sE, cE;
     sincos(E, &sE, &cE);
     const double F = (cE - e) * p.sinw + p.beta * sE * p.cosw;
     const double FE = -sE * p.sinw + p.beta * cE * p.cosw;
     const double FEE = -cE * p.sinw - p.beta * sE * p.cosw;
-    const double FEEE = -FE;
-    const double E1 = 1.0 / (1.0 - e * cE);
-    const double E2 = -e * sE * E1 * E1 * E1;
-    const double E3 = -e * cE * E1 * E1 * E1 * E1 - 3.0 * e * sE * E1 * E1 * E2;
+    const double q = 1.0 / (1.0 - e * cE), q2 = q * q, q3 = q2 * q, q4 = q2 * q2;
+    const double E1 = q;
+    const double E2 = -e * sE * q3;
+    const double E3 = -e * cE * q4 + 3.0 * e * e * sE * sE * q4 * q;
+    const double E4 = e * sE * q4 * q + 10.0 * e * e * sE * cE * q3 * q3 - 15.0 * e * e * e * sE * sE * sE * q4 * q3;
+    // F_EEE = -F_E, F_EEEE = -F_EE
     const double F1 = FE * E1;
     const double F2 = FEE * E1 * E1 + FE * E2;
-    const double F3 = FEEE * E1 * E1 * E1 + 3.0 * FEE * E1 * E2 + FE * E3;
-    Anchor r;
-    r.c0 = (p.tau * F - p.d0) / tsamp;
-    r.c1 = p.tau * p.omega * F1;
-    r.c2 = p.tau * p.omega * p.omega * tsamp * F2 * 0.5;
-    r.c3 = p.tau * p.omega * p.omega * p.omega * tsamp * tsamp * F3 * (1.0 / 6.0);
-    anc[blockIdx.y * astride + a] = r;
+    const double F3 = -FE * E1 * E1 * E1 + 3.0 * FEE * E1 * E2 + FE * E3;
+    const double F4 = -FEE * E1 * E1 * E1 * E1 - 6.0 * FE * E1 * E1 * E2 + FEE * (3.0 * E2 * E2 + 4.0 * E1 * E3) +
+                      FE * E4;
+    const double w = p.omega, ts = tsamp;
+    DelayPoly r;
+    r.c0 = (p.tau * F - p.d0) / ts;
+    r.c1 = p.tau * w * F1;
+    r.c2 = p.tau * w * w * ts * F2 * 0.5;
+    r.c3 = p.tau * w * w * w * ts * ts * F3 * (1.0 / 6.0);
+    r.c4 = p.tau * w * w * w * w * ts * ts * ts * F4 * (1.0 / 24.0);
+    return r;
 }
 
-__device__ __forceinline__ int64_t source_from_anchor(const Anchor* __restrict__ anc, int64_t j)
+__device__ __forceinline__ int64_t source_from_poly(const DelayPoly& d, int64_t j, int64_t jc)
 {
-    const int64_t a = (j + (1 << (ANCHOR_BITS - 1))) >> ANCHOR_BITS;
-    const Anchor q = anc[a];
-    const double u = (double)(j - (a << ANCHOR_BITS));
-    const double d = q.c0 + u * (q.c1 + u * (q.c2 + u * q.c3));
-    return j - (int64_t)rint(d);
+    const double u = (double)(j - jc);
+    const double dl = d.c0 + u * (d.c1 + u * (d.c2 + u * (d.c3 + u * d.c4)));
+    return j - (int64_t)rint(dl);
+}
+
+// ------------------------------------------------------------------------
+// Resident series layout.  The mean-removed series is stored as complex
+// pairs z_m = (x_2m, x_2m+1) in the tile order of pass 1: point m = n1 + R s
+// (n1 < R, s < S) sits at ((n1 / C1) S + s) C1 + n1 % C1.  Pass-1 workgroup w
+// reads columns n1 in [w C1, (w+1) C1) down all rows s; a delayed read lands
+// in the same or a neighbouring column a few rows away, so its loads stay
+// contiguous instead of touching one cache line per sample.
+template <int S, int C1>
+__device__ __forceinline__ int64_t tiled_sample(int64_t j, int lgR)
+{
+    const int64_t m = j >> 1;
+    const int64_t n1 = m & ((1ll << lgR) - 1), s = m >> lgR;
+    return ((((n1 / C1) * S + s) * C1 + (n1 % C1)) << 1) | (j & 1);
+}
+
+__global__ __launch_bounds__(NT) void k_tile_series(const float* __restrict__ in, float* __restrict__ out, int64_t M,
+                                                    int lgR, int S, int C1)
+{
+    for (int64_t m = (int64_t)blockIdx.x * NT + threadIdx.x; m < M; m += (int64_t)gridDim.x * NT) {
+        const int64_t n1 = m & ((1ll << lgR) - 1), s = m >> lgR;
+        const int64_t d = ((n1 / C1) * S + s) * C1 + (n1 % C1);
+        reinterpret_cast<float2*>(out)[d] = reinterpret_cast<const float2*>(in)[m];
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -367,40 +391,52 @@ __device__ __forceinline__ int64_t source_from_anchor(const Anchor* __restrict__
 // the inter-pass twiddle W_M^{n1 k2}.  Workgroup w owns columns
 // n1 in [w C1, (w+1) C1) and writes them as the contiguous block Y[w][k2][c].
 template <int S, int C1>
-__global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ x, int64_t n, int R, double tsamp,
-                                                      const TmplDev* __restrict__ tm,
-                                                      const Anchor* __restrict__ anchors, size_t astride,
+__global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ x, int64_t n, int R, int lgR,
+                                                      double tsamp, const TmplDev* __restrict__ tm,
                                                       float2* __restrict__ Y, size_t y_stride,
                                                       const float2* __restrict__ twS,
                                                       const float2* __restrict__ twM_lo,
                                                       const float2* __restrict__ twM_hi, int32_t* __restrict__ src_out)
 {
-    constexpr int T = C1 * S / 16, LSP = S + S / 16;
+    constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1;
     __shared__ float2 lds[C1 * LSP];
     const TmplDev p = tm[blockIdx.y];
-    const Anchor* anc = anchors + blockIdx.y * astride;
     const int tile = xcd_remap(blockIdx.x, R / C1);
     const int c0 = tile * C1;
-    const bool exact = needs_exact(p, tsamp);
 
-    for (int e = threadIdx.x; e < C1 * S; e += T) {
-        const int s = e / C1, c = e % C1;
-        const int64_t j = 2 * ((int64_t)c0 + c + (int64_t)R * s);
+    // thread t gathers tile points e = 16 t .. 16 t + 15 (row s = e / C1,
+    // column c = e % C1), i.e. samples j(e) = 2 (c0 + c + R s) and j(e) + 1;
+    // all 32 loads are issued before any is stored
+    auto jof = [&](int e) -> int64_t { return 2 * ((int64_t)c0 + (e % C1) + (int64_t)R * (e / C1)); };
+    const int e0 = 16 * (int)threadIdx.x;
+    const int64_t jlo = jof(e0), jhi = jof(e0 + 15) + 1;
+    const int64_t jc = jlo + (jhi - jlo) / 2;
+    const bool use_poly = poly_ok(p, tsamp, (double)(jhi - jc));
+    DelayPoly dp = {0, 0, 0, 0, 0};
+    if (use_poly) dp = delay_poly(p, tsamp, jc);
+    float v[32];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t j = jof(e0 + i);
         int64_t i0, i1;
-        if (!exact) {
-            i0 = source_from_anchor(anc, j);
-            i1 = source_from_anchor(anc, j + 1);
+        if (use_poly) {
+            i0 = source_from_poly(dp, j, jc);
+            i1 = source_from_poly(dp, j + 1, jc);
         } else {
             i0 = source_index(p, j, tsamp);
             i1 = source_index(p, j + 1, tsamp);
         }
-        const float y0 = (i0 >= 0 && i0 < n) ? x[i0] : 0.0f;
-        const float y1 = (i1 >= 0 && i1 < n) ? x[i1] : 0.0f;
+        v[2 * i] = (i0 >= 0 && i0 < n) ? x[tiled_sample<S, C1>(i0, lgR)] : 0.0f;
+        v[2 * i + 1] = (i1 >= 0 && i1 < n) ? x[tiled_sample<S, C1>(i1, lgR)] : 0.0f;
         if (src_out) {
             src_out[j] = (int32_t)i0;
             src_out[j + 1] = (int32_t)i1;
         }
-        lds[c * LSP + pidx(s)] = make_float2(y0, y1);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = e0 + i;
+        lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(v[2 * i], v[2 * i + 1]);
     }
     __syncthreads();
     fft_tile<S, C1>(lds, twS);
@@ -437,13 +473,16 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
                                                       const float2* __restrict__ tw2M_lo,
                                                       const float2* __restrict__ tw2M_hi)
 {
-    constexpr int T = D2 * R / 16, LSP = R + R / 16, D = D2 / 2;
+    constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2;
     __shared__ float2 lds[D2 * LSP];
     const int g = xcd_remap(blockIdx.x, S / D2);
     const float2* Ys = Y + blockIdx.y * y_stride;
     float* Ps = P + blockIdx.y * p_stride;
 
-    for (int e = threadIdx.x; e < D2 * R; e += T) {
+    float2 v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = (int)threadIdx.x + i * T;
         const int c = e % C1, q = (e / C1) % D2, w = e / (C1 * D2);
         int col;
         if (q < D) {
@@ -452,7 +491,13 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
             const int a = g * D + (q - D);
             col = (a == 0) ? S / 2 : S - a;
         }
-        lds[q * LSP + pidx(w * C1 + c)] = Ys[((size_t)w * S + col) * C1 + c];
+        v[i] = Ys[((size_t)w * S + col) * C1 + c];
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int e = (int)threadIdx.x + i * T;
+        const int c = e % C1, q = (e / C1) % D2, w = e / (C1 * D2);
+        lds[q * LSP + pidx(w * C1 + c)] = v[i];
     }
     __syncthreads();
     fft_tile<R, D2>(lds, twR);
@@ -588,8 +633,27 @@ __global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_s
 // moving i by one moves the run-j index by exactly 16 j, so every LDS address
 // is a per-thread base plus a compile-time offset.  Fold 2h adds the odd m of
 // the new fold to fold h (ascending m), the order the oracle uses.
-constexpr int HT = 1024;                 // output bins per workgroup
-constexpr int HSEG = (17 * HT) / 2 + 64; // LDS floats for the 16 runs
+constexpr int HT = 1024;                   // output bins per workgroup
+constexpr int HSEG4 = (17 * HT) / 8 + 48;  // LDS float4 slots for the 16 runs (16-byte aligned)
+constexpr int HST = (HSEG4 + NT - 1) / NT; // staging float4 per thread
+
+// One fold's threshold test and wave-ballot append of the bins above it.
+__device__ __forceinline__ void emit(bool hit, int lane, uint64_t below, uint32_t* __restrict__ counter,
+                                     uint4* __restrict__ ring, uint32_t capacity, uint32_t tid, int k,
+                                     uint32_t series_fold, float acc)
+{
+    const uint64_t mask = __ballot(hit);
+    if (mask) {
+        const int leader = __ffsll((unsigned long long)mask) - 1;
+        uint32_t rbase = 0;
+        if (lane == leader) rbase = atomicAdd(counter, (uint32_t)__popcll(mask));
+        rbase = __shfl(rbase, leader);
+        if (hit) {
+            const uint32_t idx = rbase + (uint32_t)__popcll(mask & below);
+            if (idx < capacity) ring[idx] = make_uint4(tid, (uint32_t)k, series_fold, __float_as_uint(acc));
+        }
+    }
+}
 
 template <int NF>
 __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, size_t p_stride, int64_t M,
@@ -597,60 +661,88 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
                                                 uint32_t* __restrict__ counter, float* __restrict__ sums_out)
 {
     constexpr int JSTEP = 16 >> (NF - 1);  // runs needed: multiples of 16 / harm_max
-    __shared__ float seg[HSEG];
+    constexpr int R4 = HT / NT;            // output bins per thread
+    __shared__ float4 seg4[HSEG4];
     __shared__ int s_base[17];
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int k0 = tile * HT;
     const int kend = (int)(((int64_t)k0 + HT - 1) < M ? (int64_t)k0 + HT - 1 : M);
-    const float* Ps = P + blockIdx.y * p_stride;
+    const float4* P4 = reinterpret_cast<const float4*>(P + blockIdx.y * p_stride);
 
-    // stage the runs
-    int off = 0;
+    // Run j occupies float4 slots [o_j, o_j + n_j) of LDS and holds P^ from
+    // bin 4 lo4_j on.  Flat slot f of run j reads float4 f + (lo4_j - o_j).
+    // Every thread walks the (uniform) run table; its staging loads are all
+    // independent and issued before any LDS store.
+    int o[17], sh[17];
+    {
+        int off = 0;
 #pragma unroll
-    for (int j = JSTEP; j <= 16; j += JSTEP) {
-        int lo = (j * k0 + 8) >> 4, len = ((j * kend + 8) >> 4) - lo + 1;
-        for (int i = threadIdx.x; i < len; i += NT) seg[off + i] = Ps[lo + i];
-        if (threadIdx.x == 0) s_base[j] = off - lo;
-        off += len;
+        for (int j = JSTEP; j <= 16; j += JSTEP) {
+            const int lo4 = ((j * k0 + 8) >> 4) >> 2, hi4 = ((j * kend + 8) >> 4) >> 2;
+            o[j] = off;
+            sh[j] = lo4 - off;
+            off += hi4 - lo4 + 1;
+        }
+        o[0] = off;  // total
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = JSTEP; j <= 16; j += JSTEP) s_base[j] = -4 * sh[j];
+    }
+    float4 r[HST];
+#pragma unroll
+    for (int i = 0; i < HST; ++i) {
+        const int f = (int)threadIdx.x + i * NT;
+        int s = sh[JSTEP];
+#pragma unroll
+        for (int j = 2 * JSTEP; j <= 16; j += JSTEP) s = (f >= o[j]) ? sh[j] : s;
+        float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (f < o[0]) t = P4[f + s];
+        r[i] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < HST; ++i) {
+        const int f = (int)threadIdx.x + i * NT;
+        if (f < o[0]) seg4[f] = r[i];
     }
     __syncthreads();
 
-    int base[17];
-#pragma unroll
-    for (int j = JSTEP; j <= 16; j += JSTEP) base[j] = s_base[j] + ((j * (k0 + (int)threadIdx.x) + 8) >> 4);
-
+    // Bin k = k0 + t + NT r of fold 2h adds P^[floor((jk + 8)/16)] for the
+    // odd m of the fold, j = 16 m / (2h), in ascending m.  Moving r by one
+    // moves the run-j index by exactly 16 j.
+    const float* seg = reinterpret_cast<const float*>(seg4);
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const uint32_t tid = pp.first_template_id + (uint32_t)(tmpl_base + (int)blockIdx.y);
+    const int kt = k0 + (int)threadIdx.x;
+    float acc[R4];
+    bool in[R4];
+    {
+        const int b = s_base[16] + kt;
 #pragma unroll
-    for (int r = 0; r < HT / NT; ++r) {
-        const int k = k0 + r * NT + (int)threadIdx.x;
-        const bool in = k <= kend;
-        float acc = in ? seg[base[16] + 16 * 16 * r] : 0.0f;
+        for (int r = 0; r < R4; ++r) {
+            in[r] = kt + NT * r <= kend;
+            acc[r] = in[r] ? seg[b + NT * r] : 0.0f;
+        }
+    }
 #pragma unroll
-        for (int l = 0; l < NF; ++l) {
-            if (l > 0 && in) {
+    for (int l = 0; l < NF; ++l) {
+        if (l > 0) {
 #pragma unroll
-                for (int m = 1; m < (1 << l); m += 2) {
-                    const int j = m << (4 - l);
-                    acc += seg[base[j] + 16 * j * r];
-                }
+            for (int m = 1; m < (1 << l); m += 2) {
+                const int j = m << (4 - l);
+                const int b = s_base[j] + ((j * kt + 8) >> 4);
+#pragma unroll
+                for (int r = 0; r < R4; ++r)
+                    if (in[r]) acc[r] += seg[b + 16 * j * r];
             }
-            if (sums_out && in) sums_out[(size_t)l * (M + 1) + k] = acc;
-            bool hit = in && k >= pp.klo[l] && k <= pp.khi[l] && acc > pp.thr[l];
-            uint64_t mask = __ballot(hit);
-            if (mask) {
-                int leader = __ffsll((unsigned long long)mask) - 1;
-                uint32_t rbase = 0;
-                if (lane == leader) rbase = atomicAdd(counter, (uint32_t)__popcll(mask));
-                rbase = __shfl(rbase, leader);
-                if (hit) {
-                    uint32_t idx = rbase + (uint32_t)__popcll(mask & below);
-                    if (idx < pp.capacity)
-                        ring[idx] = make_uint4(tid, (uint32_t)k, (pp.series_id << 8) | (uint32_t)l,
-                                               __float_as_uint(acc));
-                }
-            }
+        }
+#pragma unroll
+        for (int r = 0; r < R4; ++r) {
+            const int k = kt + NT * r;
+            if (sums_out && in[r]) sums_out[(size_t)l * (M + 1) + k] = acc[r];
+            const bool hit = in[r] && k >= pp.klo[l] && k <= pp.khi[l] && acc[r] > pp.thr[l];
+            emit(hit, lane, below, counter, ring, pp.capacity, tid, k, (pp.series_id << 8) | (uint32_t)l, acc[r]);
         }
     }
 }
@@ -661,9 +753,8 @@ hipError_t fft1_launch(const Geometry& g, const float* x, double tsamp, const Tm
                        const Slots& ws, int32_t* src_out, hipStream_t s)
 {
     dim3 grid(g.R / C1, nslots);
-    hipLaunchKernelGGL((k_fft1<S, C1>), grid, dim3(C1 * S / 16), 0, s, x, g.n, g.R, tsamp, tm,
-                       (const Anchor*)ws.anchors, ws.a_stride, ws.Y, ws.y_stride, g.twS, g.twM_lo, g.twM_hi,
-                       src_out);
+    hipLaunchKernelGGL((k_fft1<S, C1>), grid, dim3(C1 * S / 16), 0, s, x, g.n, g.R, g.lgR, tsamp, tm, ws.Y,
+                       ws.y_stride, g.twS, g.twM_lo, g.twM_hi, src_out);
     return hipGetLastError();
 }
 
@@ -678,8 +769,6 @@ hipError_t fft2_launch(const Geometry& g, int nslots, const Slots& ws, hipStream
 
 }  // namespace
 
-int anchor_count(int64_t n) { return (int)(((n - 1 + (1 << (ANCHOR_BITS - 1))) >> ANCHOR_BITS) + 1); }
-size_t anchor_bytes() { return sizeof(Anchor); }
 int harmsum_tile() { return HT; }
 
 hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, hipStream_t s)
@@ -697,6 +786,14 @@ hipError_t launch_mean_subtract(const float* in, float* out, int64_t n, double* 
     int64_t blocks = (n + NT - 1) / NT;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(k_subtract, dim3((unsigned)blocks), dim3(NT), 0, s, in, out, n, partial + parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_series(const Geometry& g, const float* in, float* out, hipStream_t s)
+{
+    int64_t blocks = (g.M + NT - 1) / NT;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_tile_series, dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.M, g.lgR, g.S, g.C1);
     return hipGetLastError();
 }
 
@@ -722,11 +819,6 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
     hipError_t e;
     const TmplDev* tmw = tm + tmpl_base;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    {
-        hipLaunchKernelGGL(k_anchor, dim3((unsigned)((g.nanch + NT - 1) / NT), nslots), dim3(NT), 0, s, tmw, tsamp,
-                           g.nanch, (Anchor*)ws.anchors, ws.a_stride);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    }
     switch (g.S * 32 + g.C1) {
     case 32 * 32 + 16: e = fft1_launch<32, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
     case 64 * 32 + 16: e = fft1_launch<64, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
