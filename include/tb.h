@@ -62,7 +62,10 @@ typedef struct {
     uint64_t ring_capacity;    /* candidate records kept per request (default 1<<20) */
     void* stream;              /* hipStream_t the plan launches on; NULL = a stream of its own */
     int32_t device;            /* HIP device ordinal; the plan makes it current on each call */
+    uint32_t lanes;            /* streams requests are spread over (1..16); work on different
+                                  lanes overlaps on the device.  Lane 0 is `stream`. */
     uint32_t flags;            /* reserved, 0 */
+    uint32_t reserved;         /* 0 */
 } tb_config;
 
 /* One Keplerian orbital template (Sec. 2.1): P_orb = 2 pi / Omega, tau = a sin(eps)/c,
@@ -90,7 +93,7 @@ typedef struct {
 
 /* Fills cfg with the defaults: max_log2n 24, harm_max 16, whiten_window 4096,
  * threshold_sigma 6, fmin_hz 1, fmax_hz 0, no budget, ring 1<<20, own stream,
- * device 0. */
+ * device 0, one lane. */
 void tb_default_config(tb_config* cfg);
 
 /* Creates a plan: checks cfg, makes device cfg->device current, creates or

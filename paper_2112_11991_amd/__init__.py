@@ -42,7 +42,9 @@ class TbConfig(C.Structure):
         ("ring_capacity", C.c_uint64),
         ("stream", C.c_void_p),
         ("device", C.c_int32),
+        ("lanes", C.c_uint32),
         ("flags", C.c_uint32),
+        ("reserved", C.c_uint32),
     ]
 
 
@@ -72,7 +74,7 @@ CANDIDATE_DTYPE = np.dtype(
     ]
 )
 assert CANDIDATE_DTYPE.itemsize == 32 and TEMPLATE_DTYPE.itemsize == C.sizeof(TbTemplate) == 40
-assert C.sizeof(TbConfig) == 72
+assert C.sizeof(TbConfig) == 80
 
 EXPORTS = [
     "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",

@@ -122,7 +122,17 @@ struct SlotRec {
     size_t bytes = 0;
 };
 
+struct Lane {
+    hipStream_t stream = nullptr;
+    bool own = false;
+    std::map<int, SlotRec> slots;  // workspaces by log2 n
+    double pending = 0;            // queued work of unsettled requests (template-samples)
+};
+
 struct Req {
+    int lane = 0;
+    double work = 0;      // templates x samples, for lane balancing
+    bool settled = false; // completion already subtracted from the lane's pending work
     int32_t series = -1;
     uint32_t count = 0, first = 0;
     uint64_t cap = 0;
@@ -141,13 +151,12 @@ struct Req {
 
 struct tb_plan_s {
     tb_config cfg;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // lane 0: loads, inspection, utilities
     hipStream_t copy_stream = nullptr;
-    bool own_stream = false;
+    std::vector<Lane> lanes;       // requests spread over these streams
     std::mutex mu;
     std::map<int32_t, SeriesRec> series;
     std::map<int, GeoRec> geo;     // by log2 n
-    std::map<int, SlotRec> slots;  // by log2 n
     std::map<int64_t, Req> reqs;
     int32_t next_series = 0;
     int64_t next_req = 1;
@@ -260,10 +269,11 @@ int default_batch(const tb_plan_t p, int64_t M)
     return (int)std::min<int64_t>(256, std::max<int64_t>(4, b));
 }
 
-tb_status get_slots(tb_plan_t p, const Geometry& g, Slots** out)
+tb_status get_slots(tb_plan_t p, int lane, const Geometry& g, Slots** out)
 {
-    auto it = p->slots.find(g.log2n);
-    if (it != p->slots.end()) {
+    auto& slots = p->lanes[lane].slots;
+    auto it = slots.find(g.log2n);
+    if (it != slots.end()) {
         *out = &it->second.s;
         return TB_OK;
     }
@@ -286,7 +296,7 @@ tb_status get_slots(tb_plan_t p, const Geometry& g, Slots** out)
         p->held -= rec.bytes;
         return TB_ERR_OOM;
     }
-    auto ins = p->slots.emplace(g.log2n, rec);
+    auto ins = slots.emplace(g.log2n, rec);
     *out = &ins.first->second.s;
     return TB_OK;
 }
@@ -321,11 +331,11 @@ bool valid_template(const tb_template& t)
            t.ecc >= 0.0 && t.ecc < 1.0;
 }
 
-void free_request(Req& r)
+void free_request(tb_plan_t p, Req& r)
 {
     if (r.ev0) hipEventDestroy(r.ev0);
     if (r.ev1) hipEventDestroy(r.ev1);
-    hipFree(r.dmem);
+    if (r.dmem) hipFreeAsync(r.dmem, p->lanes[r.lane].stream);
     hipHostFree(r.h_t);
     r.dmem = nullptr;
     r.h_t = nullptr;
@@ -347,8 +357,8 @@ ReqLayout req_layout(uint32_t count, uint64_t cap)
 }
 
 // Queue the kernels of all templates of a request, wave by wave.
-tb_status enqueue(tb_plan_t p, const SeriesRec& sr, Geometry* g, Slots* ws, const TmplDev* d_tm, uint32_t count,
-                  const PeakParams& pp, uint4* ring, uint32_t* counter, const Inspect& ins)
+tb_status enqueue(tb_plan_t p, hipStream_t stream, const SeriesRec& sr, Geometry* g, Slots* ws, const TmplDev* d_tm,
+                  uint32_t count, const PeakParams& pp, uint4* ring, uint32_t* counter, const Inspect& ins)
 {
     for (uint32_t w0 = 0; w0 < count; w0 += (uint32_t)ws->B) {
         int nslots = (int)std::min<uint32_t>((uint32_t)ws->B, count - w0);
@@ -361,11 +371,43 @@ tb_status enqueue(tb_plan_t p, const SeriesRec& sr, Geometry* g, Slots* ws, cons
             ev = p->prof_events.back().data();
             p->prof_templates += (uint64_t)nslots;
         }
-        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, pp, ring, counter, ins, p->stream, ev) !=
+        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, pp, ring, counter, ins, stream, ev) !=
             hipSuccess)
             return TB_ERR_DEVICE;
     }
     return TB_OK;
+}
+
+// Subtracts finished requests from their lane's pending work.
+void settle(tb_plan_t p)
+{
+    for (auto& kv : p->reqs) {
+        Req& r = kv.second;
+        if (!r.settled && hipEventQuery(r.ev1) == hipSuccess) {
+            p->lanes[r.lane].pending -= r.work;
+            r.settled = true;
+        }
+    }
+}
+
+// The lane with the least queued work.
+int pick_lane(tb_plan_t p)
+{
+    settle(p);
+    int best = 0;
+    for (int l = 1; l < (int)p->lanes.size(); ++l)
+        if (p->lanes[l].pending < p->lanes[best].pending) best = l;
+    return best;
+}
+
+hipError_t sync_lanes(tb_plan_t p)
+{
+    hipError_t e = hipSuccess;
+    for (auto& L : p->lanes) {
+        hipError_t f = hipStreamSynchronize(L.stream);
+        if (e == hipSuccess) e = f;
+    }
+    return e;
 }
 
 tb_status fetch(tb_plan_t p, Req& r)
@@ -429,7 +471,9 @@ void tb_default_config(tb_config* c)
     c->ring_capacity = 1u << 20;
     c->stream = nullptr;
     c->device = 0;
+    c->lanes = 1;
     c->flags = 0;
+    c->reserved = 0;
 }
 
 const char* tb_strerror(tb_status s)
@@ -459,7 +503,8 @@ tb_status tb_plan(const tb_config* cfg, tb_plan_t* out)
     if (!std::isfinite(c.threshold_sigma) || !std::isfinite(c.fmin_hz) || !std::isfinite(c.fmax_hz) ||
         c.fmin_hz < 0.0 || c.fmax_hz < 0.0)
         return TB_ERR_INVALID_ARG;
-    if (c.ring_capacity == 0 || c.ring_capacity > 0xffffffffull || c.batch_templates > 4096 || c.flags)
+    if (c.ring_capacity == 0 || c.ring_capacity > 0xffffffffull || c.batch_templates > 4096 || c.flags ||
+        c.reserved || c.lanes < 1 || c.lanes > 16)
         return TB_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev) return TB_ERR_DEVICE;
@@ -467,18 +512,28 @@ tb_status tb_plan(const tb_config* cfg, tb_plan_t* out)
     tb_plan_t p = new (std::nothrow) tb_plan_s();
     if (!p) return TB_ERR_OOM;
     p->cfg = c;
-    if (c.stream) {
-        p->stream = (hipStream_t)c.stream;
-    } else {
-        if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess) {
-            delete p;
-            return TB_ERR_DEVICE;
+    p->lanes.resize(c.lanes);
+    bool ok = true;
+    for (uint32_t l = 0; l < c.lanes && ok; ++l) {
+        Lane& L = p->lanes[l];
+        if (l == 0 && c.stream) {
+            L.stream = (hipStream_t)c.stream;
+        } else {
+            ok = hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking) == hipSuccess;
+            L.own = ok;
         }
-        p->own_stream = true;
     }
-    if (hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+    if (ok) p->stream = p->lanes[0].stream;
+    // keep freed request memory in the stream-ordered pool instead of returning it
+    hipMemPool_t pool = nullptr;
+    if (ok && hipDeviceGetDefaultMemPool(&pool, c.device) == hipSuccess && pool) {
+        uint64_t keep = ~0ull;
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    if (!ok || hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&p->d_partial, sizeof(double) * 1040) != hipSuccess) {
-        if (p->own_stream) hipStreamDestroy(p->stream);
+        for (auto& L : p->lanes)
+            if (L.own) hipStreamDestroy(L.stream);
         if (p->copy_stream) hipStreamDestroy(p->copy_stream);
         delete p;
         return TB_ERR_DEVICE;
@@ -494,20 +549,23 @@ tb_status tb_destroy(tb_plan_t p)
     {
         std::lock_guard<std::mutex> lk(p->mu);
         hipSetDevice(p->cfg.device);
-        hipStreamSynchronize(p->stream);
-        for (auto& kv : p->reqs) free_request(kv.second);
+        sync_lanes(p);
+        for (auto& kv : p->reqs) free_request(p, kv.second);
+        sync_lanes(p);
         for (auto& kv : p->series) hipFree(kv.second.d);
-        for (auto& kv : p->slots) {
-            hipFree(kv.second.s.Y);
-            hipFree(kv.second.s.P);
-            hipFree(kv.second.s.med);
-        }
+        for (auto& L : p->lanes)
+            for (auto& kv : L.slots) {
+                hipFree(kv.second.s.Y);
+                hipFree(kv.second.s.P);
+                hipFree(kv.second.s.med);
+            }
         for (auto& kv : p->geo) free_geometry(kv.second);
         for (auto& v : p->prof_events)
             for (auto e : v) hipEventDestroy(e);
         hipFree(p->d_partial);
         hipStreamDestroy(p->copy_stream);
-        if (p->own_stream) hipStreamDestroy(p->stream);
+        for (auto& L : p->lanes)
+            if (L.own) hipStreamDestroy(L.stream);
     }
     delete p;
     return TB_OK;
@@ -572,7 +630,7 @@ tb_status tb_unload_series(tb_plan_t p, int32_t id)
     auto it = p->series.find(id);
     if (it == p->series.end()) return TB_ERR_UNKNOWN_ID;
     TB_TRY(hipSetDevice(p->cfg.device));
-    TB_TRY(hipStreamSynchronize(p->stream));
+    TB_TRY(sync_lanes(p));
     hipFree(it->second.d);
     p->held -= it->second.bytes;
     p->series.erase(it);
@@ -595,9 +653,22 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
     Slots* ws = nullptr;
     tb_status st;
     if ((st = get_geometry(p, ilog2((uint64_t)sr.n), &g))) return st;
-    if ((st = get_slots(p, *g, &ws))) return st;
+    int lane = pick_lane(p);
+    if ((st = get_slots(p, lane, *g, &ws))) {
+        // no room for another workspace: queue behind a lane that has one
+        int other = -1;
+        for (int l = 0; l < (int)p->lanes.size(); ++l)
+            if (p->lanes[l].slots.count(g->log2n) && (other < 0 || p->lanes[l].pending < p->lanes[other].pending))
+                other = l;
+        if (st != TB_ERR_BUDGET || other < 0) return st;
+        lane = other;
+        if ((st = get_slots(p, lane, *g, &ws))) return st;
+    }
+    hipStream_t stream = p->lanes[lane].stream;
 
     Req r;
+    r.lane = lane;
+    r.work = (double)count * (double)sr.n;
     r.series = sid;
     r.count = count;
     r.first = first;
@@ -607,12 +678,13 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
     ReqLayout L = req_layout(count, r.cap);
     r.bytes = L.total;
     if ((st = reserve(p, r.bytes))) return st;
-    if (hipMalloc(&r.dmem, L.total) != hipSuccess) {
+    if (hipMallocAsync((void**)&r.dmem, L.total, stream) != hipSuccess) {
+        r.dmem = nullptr;
         p->held -= r.bytes;
         return TB_ERR_OOM;
     }
     if (count && hipHostMalloc(&r.h_t, sizeof(tb_template) * count, hipHostMallocDefault) != hipSuccess) {
-        free_request(r);
+        free_request(p, r);
         p->held -= r.bytes;
         return TB_ERR_OOM;
     }
@@ -623,23 +695,25 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
     uint4* ring = (uint4*)(r.dmem + L.off_ring);
     PeakParams pp = peak_params(p, sr.n, sr.tsamp, (uint32_t)sid, first, r.cap);
     if (hipEventCreate(&r.ev0) != hipSuccess || hipEventCreate(&r.ev1) != hipSuccess ||
-        hipEventRecord(r.ev0, p->stream) != hipSuccess || launch_fill_u32(counter, 0u, 1, p->stream) != hipSuccess ||
-        (count && hipMemcpyAsync(d_t, r.h_t, sizeof(tb_template) * count, hipMemcpyHostToDevice, p->stream) !=
+        hipEventRecord(r.ev0, stream) != hipSuccess || launch_fill_u32(counter, 0u, 1, stream) != hipSuccess ||
+        (count && hipMemcpyAsync(d_t, r.h_t, sizeof(tb_template) * count, hipMemcpyHostToDevice, stream) !=
                       hipSuccess) ||
-        launch_template_prep(d_t, count, d_tm, p->stream) != hipSuccess) {
-        free_request(r);
+        launch_template_prep(d_t, count, d_tm, stream) != hipSuccess) {
+        hipStreamSynchronize(stream);
+        free_request(p, r);
         p->held -= r.bytes;
         return TB_ERR_DEVICE;
     }
     Inspect none;
-    st = enqueue(p, sr, g, ws, d_tm, count, pp, ring, counter, none);
-    if (st == TB_OK && hipEventRecord(r.ev1, p->stream) != hipSuccess) st = TB_ERR_DEVICE;
+    st = enqueue(p, stream, sr, g, ws, d_tm, count, pp, ring, counter, none);
+    if (st == TB_OK && hipEventRecord(r.ev1, stream) != hipSuccess) st = TB_ERR_DEVICE;
     if (st) {
-        hipStreamSynchronize(p->stream);
-        free_request(r);
+        hipStreamSynchronize(stream);
+        free_request(p, r);
         p->held -= r.bytes;
         return st;
     }
+    p->lanes[lane].pending += r.work;
     int64_t rid = p->next_req++;
     p->reqs.emplace(rid, std::move(r));
     *request_id = rid;
@@ -698,8 +772,9 @@ tb_status tb_release(tb_plan_t p, int64_t rid)
     if (it == p->reqs.end()) return TB_ERR_UNKNOWN_ID;
     TB_TRY(hipSetDevice(p->cfg.device));
     TB_TRY(hipEventSynchronize(it->second.ev1));
+    if (!it->second.settled) p->lanes[it->second.lane].pending -= it->second.work;
     p->held -= it->second.bytes;
-    free_request(it->second);
+    free_request(p, it->second);
     p->reqs.erase(it);
     return TB_OK;
 }
@@ -708,7 +783,7 @@ tb_status tb_synchronize(tb_plan_t p)
 {
     if (!p) return TB_ERR_INVALID_ARG;
     TB_TRY(hipSetDevice(p->cfg.device));
-    TB_TRY(hipStreamSynchronize(p->stream));
+    TB_TRY(sync_lanes(p));
     return TB_OK;
 }
 
@@ -738,7 +813,7 @@ tb_status tb_profile(tb_plan_t p, int enable)
     std::lock_guard<std::mutex> lk(p->mu);
     if (enable) {
         TB_TRY(hipSetDevice(p->cfg.device));
-        TB_TRY(hipStreamSynchronize(p->stream));
+        TB_TRY(sync_lanes(p));
         for (auto& v : p->prof_events)
             for (auto e : v) hipEventDestroy(e);
         p->prof_events.clear();
@@ -753,7 +828,7 @@ tb_status tb_profile_read(tb_plan_t p, double ms[5], uint64_t launches[5], uint6
     if (!p) return TB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(p->mu);
     TB_TRY(hipSetDevice(p->cfg.device));
-    TB_TRY(hipStreamSynchronize(p->stream));
+    TB_TRY(sync_lanes(p));
     double acc[K_CLASSES] = {0, 0, 0, 0, 0};
     for (auto& v : p->prof_events)
         for (int k = 0; k < K_CLASSES; ++k) {
@@ -804,7 +879,7 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     Slots* ws = nullptr;
     tb_status st;
     if ((st = get_geometry(p, ilog2((uint64_t)sr.n), &g))) return st;
-    if ((st = get_slots(p, *g, &ws))) return st;
+    if ((st = get_slots(p, 0, *g, &ws))) return st;
     int nfold = ilog2(p->cfg.harm_max) + 1;
     size_t nb = (size_t)g->M + 1;
     size_t need = 256 + 256 + sizeof(uint4) * 16 + sizeof(int32_t) * (size_t)sr.n + sizeof(float) * nfold * nb +
@@ -831,7 +906,7 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
         hipMemcpyAsync(d_t, ht, sizeof(tb_template), hipMemcpyHostToDevice, p->stream) != hipSuccess ||
         launch_template_prep(d_t, 1, d_tm, p->stream) != hipSuccess)
         st = TB_ERR_DEVICE;
-    if (!st) st = enqueue(p, sr, g, ws, d_tm, 1, pp, ring, counter, ins);
+    if (!st) st = enqueue(p, p->stream, sr, g, ws, d_tm, 1, pp, ring, counter, ins);
     if (!st && hipStreamSynchronize(p->stream) != hipSuccess) st = TB_ERR_DEVICE;
     if (!st && src && hipMemcpy(src, ins.src, sizeof(int32_t) * (size_t)sr.n, hipMemcpyDeviceToHost) != hipSuccess)
         st = TB_ERR_DEVICE;

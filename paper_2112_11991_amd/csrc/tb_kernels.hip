@@ -404,22 +404,43 @@ __global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ 
     const int tile = xcd_remap(blockIdx.x, R / C1);
     const int c0 = tile * C1;
 
-    // thread t gathers tile points e = 16 t .. 16 t + 15 (row s = e / C1,
-    // column c = e % C1), i.e. samples j(e) = 2 (c0 + c + R s) and j(e) + 1;
-    // all 32 loads are issued before any is stored
+    // Tile points are grouped in chunks of 16 consecutive points e (row
+    // s = e / C1, column c = e % C1, samples j(e) = 2 (c0 + c + R s) and
+    // j(e) + 1).  Phase A: thread t expands the delay of chunk t around the
+    // chunk's middle sample and parks the polynomial in the (still unused)
+    // tile memory.  Phase B: each thread gathers points t + T i, so that a
+    // wave's loads are consecutive rows, issuing all 32 loads before using
+    // them.  Phase C: the gathered points go to the tile.
     auto jof = [&](int e) -> int64_t { return 2 * ((int64_t)c0 + (e % C1) + (int64_t)R * (e / C1)); };
-    const int e0 = 16 * (int)threadIdx.x;
-    const int64_t jlo = jof(e0), jhi = jof(e0 + 15) + 1;
-    const int64_t jc = jlo + (jhi - jlo) / 2;
-    const bool use_poly = poly_ok(p, tsamp, (double)(jhi - jc));
-    DelayPoly dp = {0, 0, 0, 0, 0};
-    if (use_poly) dp = delay_poly(p, tsamp, jc);
+    auto jmid = [&](int g) -> int64_t {
+        const int64_t jlo = jof(16 * g), jhi = jof(16 * g + 15) + 1;
+        return jlo + (jhi - jlo) / 2;
+    };
+    DelayPoly* polys = reinterpret_cast<DelayPoly*>(lds);  // T x 40 B, inside the tile
+    {
+        const int g = (int)threadIdx.x;
+        const int64_t jc = jmid(g);
+        const int64_t U = jof(16 * g + 15) + 1 - jc;
+        DelayPoly dp;
+        if (poly_ok(p, tsamp, (double)U)) {
+            dp = delay_poly(p, tsamp, jc);
+        } else {
+            dp.c0 = __builtin_nan("");  // marks a chunk evaluated exactly
+            dp.c1 = dp.c2 = dp.c3 = dp.c4 = 0.0;
+        }
+        polys[g] = dp;
+    }
+    __syncthreads();
     float v[32];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const int64_t j = jof(e0 + i);
+        const int e = (int)threadIdx.x + i * T;
+        const int g = e >> 4;
+        const DelayPoly dp = polys[g];
+        const int64_t j = jof(e);
         int64_t i0, i1;
-        if (use_poly) {
+        if (!__builtin_isnan(dp.c0)) {
+            const int64_t jc = jmid(g);
             i0 = source_from_poly(dp, j, jc);
             i1 = source_from_poly(dp, j + 1, jc);
         } else {
@@ -433,9 +454,10 @@ __global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ 
             src_out[j + 1] = (int32_t)i1;
         }
     }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const int e = e0 + i;
+        const int e = (int)threadIdx.x + i * T;
         lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(v[2 * i], v[2 * i + 1]);
     }
     __syncthreads();
@@ -529,15 +551,18 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
 // ------------------------------------------------------------------------
 // Whitening block medians: element of rank floor((n_b-1)/2) of bins
 // [1 + bW, 1 + bW + n_b), by radix selection on the IEEE bits (powers are
-// non-negative, so unsigned order is numeric order).  Four 8-bit digit
-// passes; each wave counts into its own histogram, and the digit holding the
-// rank is found with a block-wide prefix sum.
+// non-negative, so unsigned order is numeric order).  Digits: the 8 exponent
+// bits, then 8, 8 and 7 mantissa bits.  Counting uses LDS atomics into four
+// histogram copies per wave (lane & 3) to thin out collisions on the few
+// exponent values a block spans; the digit holding the rank is found with a
+// block-wide prefix sum.
 __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size_t p_stride, int64_t M, int W,
                                                float* __restrict__ med, size_t med_stride)
 {
+    constexpr int NW = NT / 64, NC = 4;
     extern __shared__ uint32_t vals[];
-    __shared__ uint32_t hist[NT / 64][256];
-    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t hist[NW * NC][256];
+    __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_digit, s_rank;
     const int b = blockIdx.x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -545,37 +570,41 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
     const int64_t start = 1 + (int64_t)b * W;
     const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
     for (int i = threadIdx.x; i < cnt; i += NT) vals[i] = __float_as_uint(Ps[start + i]);
+    uint32_t* myhist = hist[wave * NC + (lane & (NC - 1))];
     uint32_t rank = (uint32_t)(cnt - 1) / 2, prefix = 0, mask = 0;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int i = threadIdx.x; i < (NT / 64) * 256; i += NT) (&hist[0][0])[i] = 0;
+#pragma unroll
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = pass == 0 ? 23 : pass == 1 ? 15 : pass == 2 ? 7 : 0;
+        const uint32_t dmask = pass == 3 ? 127u : 255u;
+        for (int i = threadIdx.x; i < NW * NC * 256; i += NT) (&hist[0][0])[i] = 0;
         __syncthreads();
         for (int i = threadIdx.x; i < cnt; i += NT) {
-            uint32_t v = vals[i];
-            if ((v & mask) == prefix) atomicAdd(&hist[wave][(v >> shift) & 255u], 1u);
+            const uint32_t v = vals[i];
+            if ((v & mask) == prefix) atomicAdd(&myhist[(v >> shift) & dmask], 1u);
         }
         __syncthreads();
         // thread t owns digit t (NT == 256)
         uint32_t tot = 0;
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) tot += hist[w][threadIdx.x];
+        for (int w = 0; w < NW * NC; ++w) tot += hist[w][threadIdx.x];
         uint32_t inc = tot;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
-            uint32_t o = __shfl_up(inc, d);
+            const uint32_t o = __shfl_up(inc, d);
             if (lane >= d) inc += o;
         }
         if (lane == 63) wsum[wave] = inc;
         __syncthreads();
         uint32_t before = 0;
         for (int w = 0; w < wave; ++w) before += wsum[w];
-        uint32_t excl = before + inc - tot;
+        const uint32_t excl = before + inc - tot;
         if (tot && excl <= rank && rank < excl + tot) {
             s_digit = threadIdx.x;
             s_rank = rank - excl;
         }
         __syncthreads();
         prefix |= s_digit << shift;
-        mask |= 255u << shift;
+        mask |= dmask << shift;
         rank = s_rank;
         __syncthreads();
     }
@@ -635,7 +664,6 @@ __global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_s
 // the new fold to fold h (ascending m), the order the oracle uses.
 constexpr int HT = 1024;                   // output bins per workgroup
 constexpr int HSEG4 = (17 * HT) / 8 + 48;  // LDS float4 slots for the 16 runs (16-byte aligned)
-constexpr int HST = (HSEG4 + NT - 1) / NT; // staging float4 per thread
 
 // One fold's threshold test and wave-ballot append of the bins above it.
 __device__ __forceinline__ void emit(bool hit, int lane, uint64_t below, uint32_t* __restrict__ counter,
@@ -655,65 +683,78 @@ __device__ __forceinline__ void emit(bool hit, int lane, uint64_t below, uint32_
     }
 }
 
-template <int NF>
-__global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, size_t p_stride, int64_t M,
-                                                int tmpl_base, PeakParams pp, uint4* __restrict__ ring,
-                                                uint32_t* __restrict__ counter, float* __restrict__ sums_out)
+// Which of the four waves stages run j (runs are about j HT/16 bins long):
+// a balanced split for 16 harmonics, round robin otherwise.
+__host__ __device__ constexpr int run_owner(int j, int NF)
 {
-    constexpr int JSTEP = 16 >> (NF - 1);  // runs needed: multiples of 16 / harm_max
-    constexpr int R4 = HT / NT;            // output bins per thread
-    __shared__ float4 seg4[HSEG4];
-    __shared__ int s_base[17];
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int k0 = tile * HT;
-    const int kend = (int)(((int64_t)k0 + HT - 1) < M ? (int64_t)k0 + HT - 1 : M);
-    const float4* P4 = reinterpret_cast<const float4*>(P + blockIdx.y * p_stride);
+    return NF == 5 ? ((j == 16 || j == 15 || j == 3) ? 0 : (j == 14 || j == 13 || j == 5 || j == 2) ? 1
+                      : (j == 12 || j == 11 || j == 10 || j == 1) ? 2 : 3)
+         : NF == 4 ? ((j == 16 || j == 2) ? 0 : (j == 14 || j == 4) ? 1 : (j == 12 || j == 6) ? 2 : 3)
+                   : ((j / (16 >> (NF - 1))) & 3);
+}
 
-    // Run j occupies float4 slots [o_j, o_j + n_j) of LDS and holds P^ from
-    // bin 4 lo4_j on.  Flat slot f of run j reads float4 f + (lo4_j - o_j).
-    // Every thread walks the (uniform) run table; its staging loads are all
-    // independent and issued before any LDS store.
-    int o[17], sh[17];
+template <int NF, int J>
+struct StageRuns {
+    // float4 slot offset of run J within the tile's LDS segment
+    static __device__ __forceinline__ void run(const float4* __restrict__ P4, float4* seg4, int k0, int kend,
+                                               int off, int wave, int lane, int* s_base)
     {
-        int off = 0;
+        constexpr int JSTEP = 16 >> (NF - 1);
+        const int lo4 = ((J * k0 + 8) >> 4) >> 2, hi4 = ((J * kend + 8) >> 4) >> 2, n4 = hi4 - lo4 + 1;
+        if (wave == run_owner(J, NF)) {
+            constexpr int U = (J * HT / 64 + 8) / 64 + 1;  // slots per lane, n4 <= J HT / 64 + 2
+            float4 r[U];
 #pragma unroll
-        for (int j = JSTEP; j <= 16; j += JSTEP) {
-            const int lo4 = ((j * k0 + 8) >> 4) >> 2, hi4 = ((j * kend + 8) >> 4) >> 2;
-            o[j] = off;
-            sh[j] = lo4 - off;
-            off += hi4 - lo4 + 1;
+            for (int u = 0; u < U; ++u) {
+                const int i = lane + 64 * u;
+                float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if (i < n4) t = P4[lo4 + i];
+                r[u] = t;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = lane + 64 * u;
+                if (i < n4) seg4[off + i] = r[u];
+            }
+            if (lane == 0) s_base[J] = 4 * (off - lo4);
         }
-        o[0] = off;  // total
+        StageRuns<NF, J + JSTEP>::run(P4, seg4, k0, kend, off + n4, wave, lane, s_base);
     }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int j = JSTEP; j <= 16; j += JSTEP) s_base[j] = -4 * sh[j];
-    }
-    float4 r[HST];
-#pragma unroll
-    for (int i = 0; i < HST; ++i) {
-        const int f = (int)threadIdx.x + i * NT;
-        int s = sh[JSTEP];
-#pragma unroll
-        for (int j = 2 * JSTEP; j <= 16; j += JSTEP) s = (f >= o[j]) ? sh[j] : s;
-        float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (f < o[0]) t = P4[f + s];
-        r[i] = t;
-    }
-#pragma unroll
-    for (int i = 0; i < HST; ++i) {
-        const int f = (int)threadIdx.x + i * NT;
-        if (f < o[0]) seg4[f] = r[i];
-    }
-    __syncthreads();
+};
+template <int NF>
+struct StageRuns<NF, 17> {
+    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
+};
+template <int NF>
+struct StageRuns<NF, 18> {
+    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
+};
+template <int NF>
+struct StageRuns<NF, 20> {
+    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
+};
+template <int NF>
+struct StageRuns<NF, 24> {
+    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
+};
+template <int NF>
+struct StageRuns<NF, 32> {
+    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
+};
 
-    // Bin k = k0 + t + NT r of fold 2h adds P^[floor((jk + 8)/16)] for the
-    // odd m of the fold, j = 16 m / (2h), in ascending m.  Moving r by one
-    // moves the run-j index by exactly 16 j.
-    const float* seg = reinterpret_cast<const float*>(seg4);
+// Folds of the HT/NT bins k = k0 + t + NT r of one thread.  Bin k of fold
+// 2h adds P^[floor((jk + 8)/16)] for the odd m of the fold, j = 16 m / (2h),
+// in ascending m; moving r by one moves the run-j index by exactly 16 j.
+// FULL tiles need no bounds test.
+template <int NF, bool FULL>
+__device__ __forceinline__ void fold_tile(const float* seg, const int* s_base, int k0, int kend, int64_t M,
+                                          const PeakParams& pp, uint4* __restrict__ ring,
+                                          uint32_t* __restrict__ counter, float* __restrict__ sums_out,
+                                          uint32_t tid)
+{
+    constexpr int R4 = HT / NT;
     const int lane = threadIdx.x & 63;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint32_t tid = pp.first_template_id + (uint32_t)(tmpl_base + (int)blockIdx.y);
     const int kt = k0 + (int)threadIdx.x;
     float acc[R4];
     bool in[R4];
@@ -721,7 +762,7 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
         const int b = s_base[16] + kt;
 #pragma unroll
         for (int r = 0; r < R4; ++r) {
-            in[r] = kt + NT * r <= kend;
+            in[r] = FULL || kt + NT * r <= kend;
             acc[r] = in[r] ? seg[b + NT * r] : 0.0f;
         }
     }
@@ -734,7 +775,7 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
                 const int b = s_base[j] + ((j * kt + 8) >> 4);
 #pragma unroll
                 for (int r = 0; r < R4; ++r)
-                    if (in[r]) acc[r] += seg[b + 16 * j * r];
+                    if (FULL || in[r]) acc[r] += seg[b + 16 * j * r];
             }
         }
 #pragma unroll
@@ -745,6 +786,32 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
             emit(hit, lane, below, counter, ring, pp.capacity, tid, k, (pp.series_id << 8) | (uint32_t)l, acc[r]);
         }
     }
+}
+
+template <int NF>
+__global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, size_t p_stride, int64_t M,
+                                                int tmpl_base, PeakParams pp, uint4* __restrict__ ring,
+                                                uint32_t* __restrict__ counter, float* __restrict__ sums_out)
+{
+    constexpr int JSTEP = 16 >> (NF - 1);
+    __shared__ float4 seg4[HSEG4];
+    __shared__ int s_base[17];
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int k0 = tile * HT;
+    const int kend = (int)(((int64_t)k0 + HT - 1) < M ? (int64_t)k0 + HT - 1 : M);
+    const float4* P4 = reinterpret_cast<const float4*>(P + blockIdx.y * p_stride);
+
+    // Run j holds P^ from bin 4 floor(lo_j / 4) on, lo_j = floor((j k0 + 8)/16);
+    // runs are packed in ascending j; each wave stages the runs it owns.
+    StageRuns<NF, JSTEP>::run(P4, seg4, k0, kend, 0, (int)threadIdx.x >> 6, (int)threadIdx.x & 63, s_base);
+    __syncthreads();
+
+    const float* seg = reinterpret_cast<const float*>(seg4);
+    const uint32_t tid = pp.first_template_id + (uint32_t)(tmpl_base + (int)blockIdx.y);
+    if (kend == k0 + HT - 1)
+        fold_tile<NF, true>(seg, s_base, k0, kend, M, pp, ring, counter, sums_out, tid);
+    else
+        fold_tile<NF, false>(seg, s_base, k0, kend, M, pp, ring, counter, sums_out, tid);
 }
 
 // ------------------------------------------------------------------------
