@@ -1,13 +1,16 @@
 """Benchmark of the template-bank coherent orbital search on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4]
+    python bench.py [--steps K] [--warmup W] [--workload c2|c1|c3|c4|c5]
 
 One step is one pass of the whole search (resample, FFT, power, whitening,
-harmonic sum, peaks) over the workload's full template bank, with the series
+harmonic sum, peaks) over the workload's template bank, with the series
 already resident in HBM.  The default workload is the circular survey-scale
 search: one 2^23-sample series at 64 us with red noise and a pulsar, 20,000
-uniform circular templates.  Prints one JSON line on stdout; progress goes to
-stderr.  Only one GPU is used: --gpus above 1 exits with a message.
+uniform circular templates.  c4 is the batched uneven-length search (32
+series x 4096 templates, one step = all series), c5 the served request stream
+(p50/p99 latency beside throughput).  Prints one JSON line on stdout;
+progress goes to stderr.  Only one GPU is used: --gpus above 1 exits with a
+message.
 """
 from __future__ import annotations
 
@@ -25,9 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNELS = ["k_pass1 (resample + FFT pass 1)", "k_pass2 (FFT pass 2 + power)", "k_median (whitening medians)",
-           "k_whiten (whitening)", "k_harmsum (harmonic sum + peaks)"]
-KERNEL_SHORT = ["k_pass1", "k_pass2", "k_median", "k_whiten", "k_harmsum"]
+KERNELS = ["k_fft1 (delay + resample + FFT pass 1)", "k_fft2 (FFT pass 2 + R2C + power)",
+           "k_median (whitening medians)", "k_whiten (whitening)", "k_harmsum (harmonic sum + peaks)"]
+KERNEL_SHORT = ["k_fft1", "k_fft2", "k_median", "k_whiten", "k_harmsum"]
+METRIC = "templates/s (resample+FFT+harmsum+peaks) at N=2^23 FP32"
 
 
 def log(*a):
@@ -52,8 +56,8 @@ def describe(w, name):
     n = [int(s.size) for s in w.series]
     if name == "c4":
         return {"workload": "batched uneven-length search: %d series of 2^20..2^23 samples at 64 us, %d shared circular "
-                            "templates" % (len(n), len(w.templates)), "series": len(n), "samples_total": int(sum(n)),
-                "templates": int(len(w.templates))}
+                            "templates each, 16 harmonics, 6 sigma" % (len(n), len(w.templates)),
+                "series": len(n), "samples_total": int(sum(n)), "templates": int(len(w.templates))}
     kind = "elliptical" if w.templates["ecc"].max() > 0 else "circular"
     return {"workload": "%s search: one series N=2^%d at %g us, %d uniform %s templates, 16 harmonics, 6 sigma, "
                         "whitening W=4096" % (w.name, int(math.log2(n[0])), w.tsamp * 1e6, len(w.templates), kind),
@@ -71,10 +75,10 @@ def kernel_bytes(n: int, templates_per_launch: float):
     return [4.0 * n * b + 4.0 * n, 6.0 * n * b, 2.0 * n * b, 4.0 * n * b, 2.0 * n * b]
 
 
-def traffic_record(kernel: str):
+def traffic_record(kernel: str, workload_name: str):
     """Measured HBM traffic per launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel)
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload_name))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -110,33 +114,68 @@ def cpu_baseline(w, seconds_hint: float):
             "single_thread_templates_per_s": 1.0 / one}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4"])
-    ap.add_argument("--templates", type=int, default=None)
-    ap.add_argument("--batch", type=int, default=0, help="templates in flight per launch (0 = library default)")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (multi-GPU sharding is a design "
-              "note only)" % args.gpus, file=sys.stderr)
-        return 2
+def kernel_report(plan, n_avg: float, workload_name: str):
+    ms, launches, tmpl = plan.profile_read()
+    plan.profile(False)
+    per = []
+    for k in range(5):
+        L = max(1, int(launches[k]))
+        avg_ms = ms[k] / L
+        byt = kernel_bytes(int(n_avg), tmpl / L)[k]
+        per.append({"kernel": KERNEL_SHORT[k], "desc": KERNELS[k], "launches": int(launches[k]), "avg_ms": avg_ms,
+                    "total_ms": float(ms[k]), "bytes_per_launch": byt,
+                    "gbs": byt / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None})
+    dom = max(range(5), key=lambda k: ms[k])
+    d = per[dom]
+    tr = traffic_record(d["kernel"], workload_name)
+    roof = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": d["gbs"] / PEAK_HBM_GBS, "traffic": None if tr is None else tr["bytes_per_launch"],
+            "avg_launch_ms": d["avg_ms"], "templates_per_launch": tmpl / max(1, int(launches[dom]))}
+    return per, roof
 
+
+def stream_copy_gbs(plan, tb):
     import torch
 
-    import paper_2112_11991_amd as tb
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    cms = tb.tb_stream_copy(plan.handle, b.data_ptr(), a.data_ptr(), nbytes, 20)
+    return 2.0 * nbytes / (cms * 1e-3) / 1e9
 
-    log("workload", args.workload)
+
+def timed_requests(plan, sids, bank, ntemp):
+    """Submits bank[:ntemp] on every series, waits for all; templates/s."""
+    t0 = time.perf_counter()
+    rids = [plan.submit(sid, bank[:ntemp]) for sid in sids]
+    for rid in rids:
+        plan.candidates(rid)
+        plan.release(rid)
+    return len(sids) * ntemp / (time.perf_counter() - t0)
+
+
+def plain_vs_batched(tb, w, series_idx, ntemp):
+    """Templates/s of the one-template-per-launch path (each kernel launched
+    for one template, one stream) and of the batched path on the same subset."""
+    rates = {}
+    for name, kw in (("plain", dict(batch_templates=1, lanes=1)), ("batched", dict(lanes=4))):
+        with tb.Plan(whiten_window=w.whiten_window, fmin_hz=w.fmin_hz, ring_capacity=1 << 16, **kw) as plan:
+            sids = [plan.load_series(w.series[i], w.tsamp) for i in series_idx]
+            for sid in sids:
+                plan.search(sid, w.templates[:2])
+            rates[name] = timed_requests(plan, sids, w.templates, ntemp)
+    return rates
+
+
+def run_bank(args, tb, torch):
+    """c1/c2/c3/c4: every series x the whole bank per step."""
     w = workload(args.workload, args.templates)
     conf = describe(w, args.workload)
-    torch.cuda.set_device(0)
+    lanes = args.lanes or (4 if len(w.series) > 1 else 1)
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
-                   threshold_sigma=w.sigma, fmin_hz=w.fmin_hz)
+                   threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18)
     sids = [plan.load_series(s, w.tsamp) for s in w.series]
     ntemp = len(w.templates)
     nitems = ntemp * len(sids)
@@ -167,61 +206,113 @@ def main():
     ms_step = 1e3 * dt / args.steps
     log("timed %d steps: %.1f ms/step, %.0f templates/s, %d candidates/step" % (args.steps, ms_step, value,
                                                                                 ncand // max(1, args.steps)))
-
-    n_avg = float(np.mean([s.size for s in w.series]))
     samples_total = float(sum(s.size for s in w.series))
-    out = {
-        "metric": "templates/s (resample+FFT+harmsum+peaks) at N=2^23 FP32",
-        "value": value,
-        "unit": "templates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": conf,
-        "candidates_per_step": ncand // max(1, args.steps),
-        "algorithmic_gbs": 12.0 * samples_total * ntemp * args.steps / dt / 1e9,
-    }
+    out = {"metric": METRIC if args.workload == "c2" else "templates/s (%s)" % args.workload, "value": value,
+           "unit": "templates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": conf, "candidates_per_step": ncand // max(1, args.steps),
+           "algorithmic_gbs": 12.0 * samples_total * ntemp * args.steps / dt / 1e9}
     out["algorithmic_hbm_frac"] = out["algorithmic_gbs"] / PEAK_HBM_GBS
-
     if not args.no_profile:
-        ms, launches, tmpl = plan.profile_read()
-        plan.profile(False)
-        per = []
-        for k in range(5):
-            L = max(1, int(launches[k]))
-            avg_ms = ms[k] / L
-            byt = kernel_bytes(int(n_avg), tmpl / L)[k]
-            per.append({"kernel": KERNEL_SHORT[k], "desc": KERNELS[k], "launches": int(launches[k]),
-                        "avg_ms": avg_ms, "total_ms": float(ms[k]), "bytes_per_launch": byt,
-                        "gbs": byt / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None})
-        out["kernels"] = per
-        dom = max(range(5), key=lambda k: ms[k])
-        d = per[dom]
-        tr = traffic_record(d["kernel"])
-        out["roofline"] = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["gbs"], "peak": PEAK_HBM_GBS,
-                           "unit": "GB/s", "frac": d["gbs"] / PEAK_HBM_GBS,
-                           "traffic": None if tr is None else tr["bytes_per_launch"],
-                           "avg_launch_ms": d["avg_ms"], "templates_per_launch": tmpl / max(1, int(launches[dom]))}
-        # practical ceiling: a plain streaming copy of 1 GiB
-        nbytes = 1 << 30
-        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        cms = tb.tb_stream_copy(plan.handle, b.data_ptr(), a.data_ptr(), nbytes, 20)
-        out["stream_copy_gbs"] = 2.0 * nbytes / (cms * 1e-3) / 1e9
-        del a, b
+        out["kernels"], out["roofline"] = kernel_report(plan, samples_total / len(w.series), args.workload)
+        out["stream_copy_gbs"] = stream_copy_gbs(plan, tb)
     plan.close()
-
+    if args.workload == "c4" and not args.no_plain:
+        idx = list(range(min(4, len(w.series))))
+        rates = plain_vs_batched(tb, w, idx, 256)
+        out["plain_one_template_per_launch"] = {"value": rates["plain"], "unit": "templates/s",
+                                                "sample": "series %s x first 256 templates" % idx}
+        out["batched_same_subset"] = {"value": rates["batched"], "unit": "templates/s"}
+        out["batched_vs_plain"] = rates["batched"] / rates["plain"]
     if not args.no_cpu_baseline and args.workload in ("c1", "c2", "c3"):
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    return out
+
+
+def run_served(args, tb, torch):
+    """c5: Poisson request stream served by the continuous-batching loop."""
+    import synth
+    from paper_2112_11991_amd.serve import Request, serve
+
+    nreq = args.requests
+    lens, reqs = synth.request_trace(nreq)
+    series = synth.pool_series(lens)
+    tsamp = 64e-6
+    plan = tb.Plan(lanes=args.lanes or 4, ring_capacity=1 << 16, hbm_budget_bytes=200 * 10**9, fmin_hz=1.0)
+    sids = [plan.load_series(s, tsamp) for s in series]
+    for n in sorted(set(lens)):
+        plan.search(sids[lens.index(n)], reqs[0]["templates"][:8])
+    torch.cuda.synchronize()
+
+    def requests():
+        return [Request(r["t_arrival"], r["series"], r["templates"], 100000 * k) for k, r in enumerate(reqs)]
+
+    log("serving %d requests at 50/s ..." % nreq)
+    rep = serve(plan, sids, lens, requests(), realtime=True)
+    log("  p50 %.1f ms p99 %.1f ms, %.0f templates/s" % (rep.p50_ms, rep.p99_ms, rep.templates_per_s))
+    # the same requests at half the measured capacity: the latency floor
+    scale = 50.0 / (0.5 * rep.n_requests / rep.makespan_s)
+    log("serving at %.2f req/s ..." % (50.0 / scale))
+    rep2 = serve(plan, sids, lens, requests(), realtime=True, time_scale=scale)
+    log("  p50 %.1f ms p99 %.1f ms" % (rep2.p50_ms, rep2.p99_ms))
+    plan.close()
+    out = {"metric": "served templates/s and p50/p99 latency (request stream)", "value": rep.templates_per_s,
+           "unit": "templates/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": rep.makespan_s * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "served stream: %d requests, Poisson 50/s, pool of 16 series 2^20..2^24 at 64 us, "
+                                  "256-4096 templates each, 30%% elliptical" % nreq},
+           "p50_ms": rep.p50_ms, "p99_ms": rep.p99_ms,
+           "saturation": rep.as_dict(), "half_capacity": dict(rep2.as_dict(), rate_req_s=50.0 / scale)}
+    if not args.no_plain:
+        rates = {}
+        sub = requests()[:6]
+        for name, kw in (("plain", dict(batch_templates=1, lanes=1)), ("served", dict(lanes=args.lanes or 4))):
+            with tb.Plan(ring_capacity=1 << 16, **kw) as pp:
+                ps = {r.series: None for r in sub}
+                for k in ps:
+                    ps[k] = pp.load_series(series[k], tsamp)
+                    pp.search(ps[k], sub[0].templates[:2])
+                t0 = time.perf_counter()
+                rids = [pp.submit(ps[r.series], r.templates[:128]) for r in sub]
+                for rid in rids:
+                    pp.candidates(rid)
+                    pp.release(rid)
+                rates[name] = sum(min(128, len(r.templates)) for r in sub) / (time.perf_counter() - t0)
+        out["plain_one_template_per_launch"] = {"value": rates["plain"], "unit": "templates/s",
+                                                "sample": "first 6 requests, first 128 templates each"}
+        out["lanes_same_subset"] = {"value": rates["served"], "unit": "templates/s"}
+        out["served_vs_plain"] = rates["served"] / rates["plain"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--templates", type=int, default=None)
+    ap.add_argument("--requests", type=int, default=100)
+    ap.add_argument("--batch", type=int, default=0, help="templates in flight per launch (0 = library default)")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-template-per-launch comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU; --gpus %d is not supported (multi-GPU sharding is a design "
+              "note only)" % args.gpus, file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_2112_11991_amd as tb
+
+    torch.cuda.set_device(0)
+    log("workload", args.workload)
+    out = run_served(args, tb, torch) if args.workload == "c5" else run_bank(args, tb, torch)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -140,6 +140,14 @@ tb_status tb_release(tb_plan_t plan, int64_t request_id);
 /* Blocks until every queued request of the plan has finished. */
 tb_status tb_synchronize(tb_plan_t plan);
 
+/* Device memory the plan holds (series, workspaces, tables, queued requests)
+ * and its current HBM budget (0 = none).  Either pointer may be NULL. */
+tb_status tb_memory(tb_plan_t plan, uint64_t* held_bytes, uint64_t* budget_bytes);
+
+/* Changes the admission budget; 0 removes it.  Memory already held is kept;
+ * later allocations that would exceed the budget fail with TB_ERR_BUDGET. */
+tb_status tb_set_budget(tb_plan_t plan, uint64_t budget_bytes);
+
 /* Static description of a status. */
 const char* tb_strerror(tb_status status);
 

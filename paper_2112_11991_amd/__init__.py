@@ -79,7 +79,8 @@ assert C.sizeof(TbConfig) == 80
 EXPORTS = [
     "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
-    "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy",
+    "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
+    "tb_set_budget",
 ]
 
 
@@ -124,6 +125,8 @@ def _load():
     L.tb_profile.argtypes = [vp, C.c_int]
     L.tb_profile_read.argtypes = [vp, vp, vp, P(u64)]
     L.tb_stream_copy.argtypes = [vp, vp, vp, u64, u32, P(C.c_double)]
+    L.tb_memory.argtypes = [vp, P(u64), P(u64)]
+    L.tb_set_budget.argtypes = [vp, u64]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tb_default_config", "tb_strerror"):
@@ -268,6 +271,18 @@ def tb_stream_copy(plan: int, dst: int, src: int, nbytes: int, reps: int = 10) -
     return ms.value
 
 
+def tb_memory(plan: int):
+    """(held bytes, budget bytes)."""
+    h = C.c_uint64(0)
+    b = C.c_uint64(0)
+    _check(_L.tb_memory(C.c_void_p(plan), C.byref(h), C.byref(b)), "tb_memory")
+    return int(h.value), int(b.value)
+
+
+def tb_set_budget(plan: int, budget_bytes: int) -> None:
+    _check(_L.tb_set_budget(C.c_void_p(plan), int(budget_bytes)), "tb_set_budget")
+
+
 def tb_inspect_template(plan: int, series_id: int, template, n: int, harm_max: int = 16, whiten_window: int = 4096,
                         want=("src", "power", "medians", "sums")):
     t = TbTemplate(*[float(v) for v in template])
@@ -359,6 +374,12 @@ class Plan:
 
     def request_ms(self, rid) -> float:
         return tb_last_request_ms(self.handle, rid)
+
+    def memory(self):
+        return tb_memory(self.handle)
+
+    def set_budget(self, budget_bytes):
+        tb_set_budget(self.handle, budget_bytes)
 
     def profile(self, enable=True):
         tb_profile(self.handle, enable)

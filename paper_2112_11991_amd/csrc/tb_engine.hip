@@ -649,6 +649,9 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
     if (sit == p->series.end()) return TB_ERR_UNKNOWN_ID;
     TB_TRY(hipSetDevice(p->cfg.device));
     const SeriesRec& sr = sit->second;
+    // sample indices stay 32-bit: the delay may not exceed 2^29 samples
+    for (uint32_t i = 0; i < count; ++i)
+        if (!(2.0 * t[i].tau_lts * (1.0 + t[i].ecc) / sr.tsamp <= (double)(1 << 29))) return TB_ERR_INVALID_ARG;
     Geometry* g = nullptr;
     Slots* ws = nullptr;
     tb_status st;
@@ -787,6 +790,23 @@ tb_status tb_synchronize(tb_plan_t p)
     return TB_OK;
 }
 
+tb_status tb_memory(tb_plan_t p, uint64_t* held, uint64_t* budget)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (held) *held = p->held;
+    if (budget) *budget = p->cfg.hbm_budget_bytes;
+    return TB_OK;
+}
+
+tb_status tb_set_budget(tb_plan_t p, uint64_t budget)
+{
+    if (!p) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->cfg.hbm_budget_bytes = budget;
+    return TB_OK;
+}
+
 tb_status tb_thresholds(tb_plan_t p, float out[5])
 {
     if (!p || !out) return TB_ERR_INVALID_ARG;
@@ -875,6 +895,7 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     if (sit == p->series.end()) return TB_ERR_UNKNOWN_ID;
     TB_TRY(hipSetDevice(p->cfg.device));
     const SeriesRec& sr = sit->second;
+    if (!(2.0 * t->tau_lts * (1.0 + t->ecc) / sr.tsamp <= (double)(1 << 29))) return TB_ERR_INVALID_ARG;
     Geometry* g = nullptr;
     Slots* ws = nullptr;
     tb_status st;

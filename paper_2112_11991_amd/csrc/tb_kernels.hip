@@ -374,6 +374,39 @@ __device__ __forceinline__ int64_t tiled_sample(int64_t j, int lgR)
     return ((((n1 / C1) * S + s) * C1 + (n1 % C1)) << 1) | (j & 1);
 }
 
+template <int S, int C1>
+__device__ __forceinline__ int tiled_sample32(int j, int lgR)
+{
+    const int m = j >> 1;
+    const int n1 = m & ((1 << lgR) - 1), s = m >> lgR;
+    return ((((n1 / C1) * S + s) * C1 + (n1 % C1)) << 1) | (j & 1);
+}
+
+// Pass-1 gather for templates whose delay polynomial would not meet the
+// accuracy bound: Kepler solve at every sample, written straight to the tile.
+// Kept out of line so that its FP64 code does not crowd the common path.
+template <int S, int C1>
+__device__ __attribute__((noinline)) void gather_exact(const float* __restrict__ x, int n, int c0, int R, int lgR,
+                                                       double tsamp, const TmplDev* __restrict__ tp, float2* lds,
+                                                       int32_t* __restrict__ src_out)
+{
+    constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1;
+    const TmplDev p = *tp;
+#pragma unroll 1
+    for (int e = threadIdx.x; e < C1 * S; e += T) {
+        const int j = 2 * (c0 + (e % C1) + R * (e / C1));
+        const int i0 = (int)source_index(p, j, tsamp), i1 = (int)source_index(p, j + 1, tsamp);
+        const bool ok0 = (unsigned)i0 < (unsigned)n, ok1 = (unsigned)i1 < (unsigned)n;
+        const float y0 = ok0 ? x[tiled_sample32<S, C1>(i0, lgR)] : 0.0f;
+        const float y1 = ok1 ? x[tiled_sample32<S, C1>(i1, lgR)] : 0.0f;
+        if (src_out) {
+            src_out[j] = i0;
+            src_out[j + 1] = i1;
+        }
+        lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(y0, y1);
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_tile_series(const float* __restrict__ in, float* __restrict__ out, int64_t M,
                                                     int lgR, int S, int C1)
 {
@@ -406,59 +439,55 @@ __global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ 
 
     // Tile points are grouped in chunks of 16 consecutive points e (row
     // s = e / C1, column c = e % C1, samples j(e) = 2 (c0 + c + R s) and
-    // j(e) + 1).  Phase A: thread t expands the delay of chunk t around the
-    // chunk's middle sample and parks the polynomial in the (still unused)
-    // tile memory.  Phase B: each thread gathers points t + T i, so that a
-    // wave's loads are consecutive rows, issuing all 32 loads before using
-    // them.  Phase C: the gathered points go to the tile.
-    auto jof = [&](int e) -> int64_t { return 2 * ((int64_t)c0 + (e % C1) + (int64_t)R * (e / C1)); };
-    auto jmid = [&](int g) -> int64_t {
-        const int64_t jlo = jof(16 * g), jhi = jof(16 * g + 15) + 1;
+    // j(e) + 1); every chunk spans the same number of samples, so whether the
+    // delay polynomial is accurate enough is decided once per workgroup.
+    // Phase A: thread t expands the delay of chunk t around the chunk's middle
+    // sample and parks the polynomial in the (still unused) tile memory.
+    // Phase B: each thread gathers points t + T i, so that a wave's loads are
+    // consecutive rows, issuing all 32 loads before using them.  Phase C: the
+    // gathered points go to the tile.  Sample indices fit in 32 bits (n <= 2^24
+    // and the host bounds the delay).
+    auto jof = [&](int e) -> int { return 2 * (c0 + (e % C1) + R * (e / C1)); };
+    auto jmid = [&](int g) -> int {
+        const int jlo = jof(16 * g), jhi = jof(16 * g + 15) + 1;
         return jlo + (jhi - jlo) / 2;
     };
-    DelayPoly* polys = reinterpret_cast<DelayPoly*>(lds);  // T x 40 B, inside the tile
-    {
-        const int g = (int)threadIdx.x;
-        const int64_t jc = jmid(g);
-        const int64_t U = jof(16 * g + 15) + 1 - jc;
-        DelayPoly dp;
-        if (poly_ok(p, tsamp, (double)U)) {
-            dp = delay_poly(p, tsamp, jc);
-        } else {
-            dp.c0 = __builtin_nan("");  // marks a chunk evaluated exactly
-            dp.c1 = dp.c2 = dp.c3 = dp.c4 = 0.0;
-        }
-        polys[g] = dp;
-    }
-    __syncthreads();
-    float v[32];
+    const int n32 = (int)n;
+    const int half_span = jof(15) + 1 - jmid(0);
+    if (poly_ok(p, tsamp, (double)half_span)) {
+        DelayPoly* polys = reinterpret_cast<DelayPoly*>(lds);  // T x 40 B, inside the tile
+        polys[threadIdx.x] = delay_poly(p, tsamp, jmid((int)threadIdx.x));
+        __syncthreads();
+        float v[32];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = (int)threadIdx.x + i * T;
-        const int g = e >> 4;
-        const DelayPoly dp = polys[g];
-        const int64_t j = jof(e);
-        int64_t i0, i1;
-        if (!__builtin_isnan(dp.c0)) {
-            const int64_t jc = jmid(g);
-            i0 = source_from_poly(dp, j, jc);
-            i1 = source_from_poly(dp, j + 1, jc);
-        } else {
-            i0 = source_index(p, j, tsamp);
-            i1 = source_index(p, j + 1, tsamp);
+        for (int i = 0; i < 16; ++i) {
+            const int e = (int)threadIdx.x + i * T;
+            const int g = e >> 4;
+            const DelayPoly dp = polys[g];
+            const int j = jof(e);
+            const double u = (double)(j - jmid(g));
+            const double d0 = dp.c0 + u * (dp.c1 + u * (dp.c2 + u * (dp.c3 + u * dp.c4)));
+            const double u1 = u + 1.0;
+            const double d1 = dp.c0 + u1 * (dp.c1 + u1 * (dp.c2 + u1 * (dp.c3 + u1 * dp.c4)));
+            const int i0 = j - (int)rint(d0), i1 = j + 1 - (int)rint(d1);
+            const bool ok0 = (unsigned)i0 < (unsigned)n32, ok1 = (unsigned)i1 < (unsigned)n32;
+            const float y0 = x[tiled_sample32<S, C1>(ok0 ? i0 : 0, lgR)];
+            const float y1 = x[tiled_sample32<S, C1>(ok1 ? i1 : 0, lgR)];
+            v[2 * i] = ok0 ? y0 : 0.0f;
+            v[2 * i + 1] = ok1 ? y1 : 0.0f;
+            if (src_out) {
+                src_out[j] = i0;
+                src_out[j + 1] = i1;
+            }
         }
-        v[2 * i] = (i0 >= 0 && i0 < n) ? x[tiled_sample<S, C1>(i0, lgR)] : 0.0f;
-        v[2 * i + 1] = (i1 >= 0 && i1 < n) ? x[tiled_sample<S, C1>(i1, lgR)] : 0.0f;
-        if (src_out) {
-            src_out[j] = (int32_t)i0;
-            src_out[j + 1] = (int32_t)i1;
-        }
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = (int)threadIdx.x + i * T;
-        lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(v[2 * i], v[2 * i + 1]);
+        for (int i = 0; i < 16; ++i) {
+            const int e = (int)threadIdx.x + i * T;
+            lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(v[2 * i], v[2 * i + 1]);
+        }
+    } else {
+        gather_exact<S, C1>(x, n32, c0, R, lgR, tsamp, tm + blockIdx.y, lds, src_out);
     }
     __syncthreads();
     fft_tile<S, C1>(lds, twS);

@@ -1,0 +1,92 @@
+"""Lanes and the continuous-batching loop: every request's result is the same
+alone and in the mix, also when the HBM budget makes requests wait."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tb():
+    import paper_2112_11991_amd as tb
+
+    return tb
+
+
+def _pool():
+    rng = np.random.default_rng(501)
+    lens = [1 << 15, 1 << 16, 1 << 17]
+    series = []
+    for i, n in enumerate(lens):
+        x = rng.standard_normal(n)
+        if i == 1:
+            x = synth.inject(x, synth.pulse_train(n, 64e-6, 0.009, 0.05, synth.Orbit(900.0, 0.2, 1.0)), 30.0)
+        series.append(x.astype(np.float32))
+    return lens, series
+
+
+def _trace(n_req=12, seed=502):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n_req):
+        cnt = int(rng.integers(16, 160))
+        if rng.uniform() < 0.3:
+            tm = synth.uniform_templates(rng, cnt, (0.3, 2.0), (0.0, 0.5), ecc_max=0.1)
+        else:
+            tm = synth.uniform_templates(rng, cnt, (0.3, 2.0), (0.0, 0.5))
+        reqs.append((float(i) * 0.002, int(rng.integers(0, 3)), tm, 10000 * i))
+    return reqs
+
+
+def _alone(tb, series, reqs):
+    out = []
+    with tb.Plan(fmin_hz=2.0, ring_capacity=1 << 16) as plan:
+        sids = [plan.load_series(x, 64e-6) for x in series]
+        for _, s, tm, first in reqs:
+            out.append(plan.search(sids[s], tm, first_template_id=first))
+    return out
+
+
+def test_lanes_give_identical_results(tb):
+    lens, series = _pool()
+    reqs = _trace()
+    ref = _alone(tb, series, reqs)
+    with tb.Plan(fmin_hz=2.0, ring_capacity=1 << 16, lanes=3) as plan:
+        sids = [plan.load_series(x, 64e-6) for x in series]
+        rids = [plan.submit(sids[s], tm, first) for _, s, tm, first in reqs]
+        got = []
+        for rid in rids:
+            c, _ = plan.candidates(rid)
+            plan.release(rid)
+            got.append(c)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("tight_budget", [False, True])
+def test_served_results_equal_alone(tb, tight_budget):
+    from paper_2112_11991_amd.serve import Request, serve
+
+    lens, series = _pool()
+    reqs = _trace(n_req=16, seed=503)
+    ref = _alone(tb, series, reqs)
+    with tb.Plan(fmin_hz=2.0, ring_capacity=1 << 16, lanes=2) as plan:
+        sids = [plan.load_series(x, 64e-6) for x in series]
+        if tight_budget:
+            # give both lanes their workspaces for every length, then leave room
+            # for about two requests in flight
+            warm = [plan.submit(sid, reqs[0][2][:2]) for sid in sids for _ in range(2)]
+            for rid in warm:
+                plan.candidates(rid)
+                plan.release(rid)
+            held, _ = plan.memory()
+            plan.set_budget(held + int(2.5 * ((1 << 16) * 16 + 32768)))
+        rq = [Request(t, s, tm, first) for t, s, tm, first in reqs]
+        rep = serve(plan, sids, lens, rq, realtime=False)
+    assert rep.n_requests == len(reqs)
+    if tight_budget:
+        assert rep.budget_waits > 0 and rep.max_in_flight <= 2
+    for r, a in zip(rq, ref):
+        assert np.array_equal(r.candidates, a)
