@@ -52,6 +52,9 @@ def workload(name: str, templates: int | None):
     raise SystemExit("unknown workload " + name)
 
 
+DEFAULT_TILE = 16384  # FFT points per workgroup when the plan chooses
+
+
 def describe(w, name):
     n = [int(s.size) for s in w.series]
     if name == "c4":
@@ -173,9 +176,11 @@ def run_bank(args, tb, torch):
     """c1/c2/c3/c4: every series x the whole bank per step."""
     w = workload(args.workload, args.templates)
     conf = describe(w, args.workload)
+    conf["tile_points"] = args.tile or DEFAULT_TILE
     lanes = args.lanes or (4 if len(w.series) > 1 else 1)
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
-                   threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18)
+                   threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18,
+                   tile_points=args.tile)
     sids = [plan.load_series(s, w.tsamp) for s in w.series]
     ntemp = len(w.templates)
     nitems = ntemp * len(sids)
@@ -296,6 +301,7 @@ def main():
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--batch", type=int, default=0, help="templates in flight per launch (0 = library default)")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0, help="FFT points per workgroup, 8192 or 16384 (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")

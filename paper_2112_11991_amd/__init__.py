@@ -44,7 +44,7 @@ class TbConfig(C.Structure):
         ("device", C.c_int32),
         ("lanes", C.c_uint32),
         ("flags", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("tile_points", C.c_uint32),
     ]
 
 

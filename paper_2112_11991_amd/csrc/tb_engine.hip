@@ -122,6 +122,16 @@ struct SlotRec {
     size_t bytes = 0;
 };
 
+void free_slots(Slots& s)
+{
+    hipFree(s.Y);
+    hipFree(s.P);
+    hipFree(s.med);
+    hipFree(s.poly);
+    hipFree(s.pok);
+    s = Slots();
+}
+
 struct Lane {
     hipStream_t stream = nullptr;
     bool own = false;
@@ -210,6 +220,22 @@ std::vector<float2> twiddles(int64_t count, double num, double den)
     return t;
 }
 
+// Radix-16 stage twiddles W_{16 NS}^{r k}, r = 1..15, for k < NS and every
+// stride NS = 2, 4, ..., ns_max, in the order the kernels index them (the
+// table of a longer transform extends that of a shorter one).
+std::vector<float2> stage_twiddles(int ns_max)
+{
+    std::vector<float2> t;
+    t.reserve(15 * (2 * (size_t)ns_max));
+    for (int ns = 2; ns <= ns_max; ns *= 2)
+        for (int k = 0; k < ns; ++k)
+            for (int r = 1; r < 16; ++r) {
+                double a = -2.0 * kPi * (double)(r * k) / (16.0 * ns);
+                t.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+            }
+    return t;
+}
+
 tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
 {
     auto it = p->geo.find(log2n);
@@ -222,8 +248,9 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     g.log2n = log2n;
     g.n = (int64_t)1 << log2n;
     g.M = g.n / 2;
-    const int64_t TE = std::min<int64_t>(16384, g.M);
-    g.R = (int)std::max<int64_t>(16, g.M / 16384);
+    g.TE = p->cfg.tile_points ? (int)p->cfg.tile_points : 16384;
+    const int64_t TE = std::min<int64_t>(g.TE, g.M);
+    g.R = (int)std::max<int64_t>(16, g.M / g.TE);
     g.S = (int)(g.M / g.R);
     g.C1 = (int)(TE / g.S);
     g.lgR = ilog2((uint64_t)g.R);
@@ -234,10 +261,8 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     int64_t hi = std::max<int64_t>(1, g.M >> TW_LO_BITS);
     std::vector<float2> v;
     tb_status st;
-    v = twiddles(g.S, 1.0, (double)g.S);
-    if ((st = upload_table(v, &g.twS, &rec.bytes))) return st;
-    v = twiddles(g.R, 1.0, (double)g.R);
-    if ((st = upload_table(v, &g.twR, &rec.bytes))) return st;
+    v = stage_twiddles(std::max(2, std::max(g.S, g.R) / 16));
+    if ((st = upload_table(v, &g.twst, &rec.bytes))) return st;
     v = twiddles(1 << TW_LO_BITS, 1.0, (double)g.M);
     if ((st = upload_table(v, &g.twM_lo, &rec.bytes))) return st;
     v = twiddles(hi, (double)(1 << TW_LO_BITS), (double)g.M);
@@ -254,8 +279,7 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
 
 void free_geometry(GeoRec& r)
 {
-    hipFree(r.g.twS);
-    hipFree(r.g.twR);
+    hipFree(r.g.twst);
     hipFree(r.g.twM_lo);
     hipFree(r.g.twM_hi);
     hipFree(r.g.tw2M_lo);
@@ -283,16 +307,17 @@ tb_status get_slots(tb_plan_t p, int lane, const Geometry& g, Slots** out)
     s.y_stride = (size_t)g.M;
     s.p_stride = ((size_t)g.M + 1 + 63) & ~(size_t)63;
     s.med_stride = ((size_t)g.nblk + 63) & ~(size_t)63;
+    s.poly_stride = (size_t)std::min<int64_t>(g.TE, g.M) / 16;
     size_t by = sizeof(float2) * s.y_stride * s.B, bp = sizeof(float) * s.p_stride * s.B,
-           bm = sizeof(float) * s.med_stride * s.B;
-    rec.bytes = by + bp + bm;
+           bm = sizeof(float) * s.med_stride * s.B, bq = sizeof(ChunkPoly) * s.poly_stride * s.B,
+           bk = sizeof(int32_t) * (size_t)s.B;
+    rec.bytes = by + bp + bm + bq + bk;
     tb_status st = reserve(p, rec.bytes);
     if (st) return st;
     if (hipMalloc(&s.Y, by) != hipSuccess || hipMalloc(&s.P, bp) != hipSuccess ||
-        hipMalloc(&s.med, bm) != hipSuccess) {
-        hipFree(s.Y);
-        hipFree(s.P);
-        hipFree(s.med);
+        hipMalloc(&s.med, bm) != hipSuccess || hipMalloc(&s.poly, bq) != hipSuccess ||
+        hipMalloc(&s.pok, bk) != hipSuccess) {
+        free_slots(s);
         p->held -= rec.bytes;
         return TB_ERR_OOM;
     }
@@ -473,7 +498,7 @@ void tb_default_config(tb_config* c)
     c->device = 0;
     c->lanes = 1;
     c->flags = 0;
-    c->reserved = 0;
+    c->tile_points = 0;
 }
 
 const char* tb_strerror(tb_status s)
@@ -504,7 +529,7 @@ tb_status tb_plan(const tb_config* cfg, tb_plan_t* out)
         c.fmin_hz < 0.0 || c.fmax_hz < 0.0)
         return TB_ERR_INVALID_ARG;
     if (c.ring_capacity == 0 || c.ring_capacity > 0xffffffffull || c.batch_templates > 4096 || c.flags ||
-        c.reserved || c.lanes < 1 || c.lanes > 16)
+        (c.tile_points != 0 && c.tile_points != 8192 && c.tile_points != 16384) || c.lanes < 1 || c.lanes > 16)
         return TB_ERR_INVALID_ARG;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev) return TB_ERR_DEVICE;
@@ -554,11 +579,7 @@ tb_status tb_destroy(tb_plan_t p)
         sync_lanes(p);
         for (auto& kv : p->series) hipFree(kv.second.d);
         for (auto& L : p->lanes)
-            for (auto& kv : L.slots) {
-                hipFree(kv.second.s.Y);
-                hipFree(kv.second.s.P);
-                hipFree(kv.second.s.med);
-            }
+            for (auto& kv : L.slots) free_slots(kv.second.s);
         for (auto& kv : p->geo) free_geometry(kv.second);
         for (auto& v : p->prof_events)
             for (auto e : v) hipEventDestroy(e);
@@ -582,7 +603,7 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
     SeriesRec r;
     r.n = (int64_t)n;
     r.tsamp = tsamp;
-    r.bytes = sizeof(float) * n;
+    r.bytes = sizeof(float) * (n + SERIES_PAD);
     tb_status st = reserve(p, r.bytes);
     if (st) return st;
     if (hipMalloc(&r.d, r.bytes) != hipSuccess) {
@@ -598,7 +619,7 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
     }
     // staging: [0, n) raw copy (host input), [n, 2n) mean-removed natural order
     float* staging = nullptr;
-    if (hipMalloc(&staging, 2 * r.bytes) != hipSuccess) {
+    if (hipMalloc(&staging, 2 * sizeof(float) * n) != hipSuccess) {
         hipFree(r.d);
         p->held -= r.bytes;
         return TB_ERR_OOM;
@@ -606,11 +627,12 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
     const float* src = data;
     hipError_t e = hipSuccess;
     if (flags == TB_MEM_HOST) {
-        e = hipMemcpyAsync(staging, data, r.bytes, hipMemcpyHostToDevice, p->stream);
+        e = hipMemcpyAsync(staging, data, sizeof(float) * n, hipMemcpyHostToDevice, p->stream);
         src = staging;
     }
     if (e == hipSuccess) e = launch_mean_subtract(src, staging + n, r.n, p->d_partial, p->stream);
     if (e == hipSuccess) e = launch_tile_series(*g, staging + n, r.d, p->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(r.d + n, 0, sizeof(float) * SERIES_PAD, p->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     hipFree(staging);
     if (e != hipSuccess) {

@@ -19,24 +19,35 @@ struct TmplDev {
 static_assert(sizeof(TmplDev) == 64, "TmplDev layout");
 
 // Two-pass FFT geometry of a real series of n = 2M samples packed as M
-// complex points, M = R * S.  Each workgroup holds TE = min(16384, M) points:
-// pass 1 does S-point transforms over the strided index (C1 = TE/S columns
-// per workgroup), pass 2 R-point transforms over D2 = TE/R columns (D2/2
-// mirrored pairs) followed by the real-to-complex split and |X|^2.
+// complex points, M = R * S.  Each workgroup holds min(TE, M) points, TE the
+// tile size (16384, or 8192 for two workgroups per CU): pass 1 does S-point
+// transforms over the strided index (C1 = TE/S columns per workgroup), pass 2
+// R-point transforms over D2 = TE/R columns (D2/2 mirrored pairs) followed by
+// the real-to-complex split and |X|^2.
 struct Geometry {
     int log2n = 0;
     int64_t n = 0, M = 0;
+    int TE = 0;
     int S = 0, R = 0, C1 = 0, D2 = 0, lgR = 0;
     int W = 0;             // whitening window (bins per median block)
     int nblk = 0;          // whitening blocks
     int htile = 0;         // harmonic-sum output bins per workgroup
-    float2* twS = nullptr; // W_S^r, r < S
-    float2* twR = nullptr; // W_R^r, r < R
+    float2* twst = nullptr;                        // radix-16 stage twiddles, every stride
     float2* twM_lo = nullptr, *twM_hi = nullptr;   // W_M^q split in 2^10 x rest
     float2* tw2M_lo = nullptr, *tw2M_hi = nullptr; // W_2M^k likewise
 };
 
 constexpr int TW_LO_BITS = 10;
+constexpr int TWST_NS_MAX = 1024;           // largest stage stride (16384-point transforms)
+constexpr int SERIES_PAD = 64;              // zero samples after a resident series
+
+// Fourth-order expansion of the sample delay around sample jmid (one per
+// chunk of 16 pass-1 tile points), 48 bytes so that records stay 16-B aligned.
+struct ChunkPoly {
+    double c0, c1, c2, c3, c4;
+    int32_t jmid, pad;
+};
+static_assert(sizeof(ChunkPoly) == 48, "ChunkPoly layout");
 
 // Per-launch search parameters of the harmonic sum / threshold stage.
 struct PeakParams {
@@ -58,6 +69,9 @@ struct Slots {
     size_t p_stride = 0;
     float* med = nullptr;  // block medians, B x nblk
     size_t med_stride = 0;
+    ChunkPoly* poly = nullptr;  // delay polynomials, B x (tile points / 16)
+    size_t poly_stride = 0;
+    int32_t* pok = nullptr;     // per slot: polynomials accurate enough
 };
 
 // Optional per-stage outputs (template slot 0 only).

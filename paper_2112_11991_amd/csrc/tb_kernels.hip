@@ -10,13 +10,14 @@
 // tiles and its L2 sees neighbouring addresses.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tb_internal.h"
 
 namespace tb {
 namespace {
 
 constexpr int NT = 256;   // threads per workgroup
-constexpr int PAD = 1;    // LDS column padding (complex elements)
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
@@ -69,6 +70,14 @@ __device__ __forceinline__ int64_t source_index(const TmplDev& p, int64_t j, dou
 {
     double d = (roemer(p, (double)j * tsamp) - p.d0) / tsamp;
     return j - (int64_t)rint(d);
+}
+
+// Nearest integer of d (ties to even, as rint) for |d| < 2^31: adding
+// 1.5 * 2^52 leaves the rounded value in the low mantissa bits.
+__device__ __forceinline__ int rint_i32(double d)
+{
+    const double t = d + 6755399441055744.0;
+    return __double2loint(t);
 }
 
 __global__ void k_template_prep(const tb_template* __restrict__ t, uint32_t count, TmplDev* __restrict__ out)
@@ -151,7 +160,7 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t count)
 // transforms them there and writes them back in Stockham order, so two LDS
 // passes per stage.  Columns are padded by one element every 16 so that the
 // strided stores of the early stages spread over the banks.  Forward sign,
-// natural order in and out.  Twiddles W_L^r come from an FP64-built table.
+// natural order in and out.  Twiddles come from an FP64-built table.
 template <int L>
 struct Log2 {
     static constexpr int value = 1 + Log2<L / 2>::value;
@@ -238,22 +247,32 @@ __device__ __forceinline__ void dft<16>(float2* v)
     for (int i = 0; i < 16; ++i) v[i] = t[i];
 }
 
+// Radix-16 stage twiddles W_{16 NS}^{r k} (r = 1..15, k < NS) for every
+// stride NS = 2, 4, ..., TWST_NS_MAX of a Stockham stage, 15 consecutive
+// entries per k and the tables of successive NS back to back.  They depend
+// only on NS, so one table serves every transform length.
+__device__ __forceinline__ constexpr int twst_offset(int NS) { return 15 * (NS - 2); }
+
+// One Stockham stage.  Element addresses are pidx(a) + pidx(b) with a < b's
+// stride (both powers of two), which equals pidx(a + b); writing them that way
+// leaves one address per butterfly and compile-time offsets for the rest.
 template <int L, int C, int RAD, int NS>
-__device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict__ tw)
+__device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict__ twst)
 {
+    static_assert(NS == 1 || RAD == 16, "only radix-16 stages carry twiddles");
     constexpr int T = C * L / 16, BPT = 16 / RAD, LR = L / RAD, LSP = L + L / 16 + 1;
-    constexpr int TWS = L / (RAD * NS);
     float2 v[16];
 #pragma unroll
     for (int u = 0; u < BPT; ++u) {
         const int bi = threadIdx.x + u * T;
         const int c = bi / LR, j = bi % LR, k = j % NS;
-        const float2* col = lds + c * LSP;
+        const float2* src = lds + c * LSP + pidx(j);
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) v[u * RAD + r] = col[pidx(j + r * LR)];
+        for (int r = 0; r < RAD; ++r) v[u * RAD + r] = src[pidx(r * LR)];
         if (NS > 1) {
+            const float2* tw = twst + twst_offset(NS) + 15 * k;
 #pragma unroll
-            for (int r = 1; r < RAD; ++r) v[u * RAD + r] = cmul(v[u * RAD + r], tw[r * k * TWS]);
+            for (int r = 1; r < RAD; ++r) v[u * RAD + r] = cmul(v[u * RAD + r], tw[r - 1]);
         }
         dft<RAD>(v + u * RAD);
     }
@@ -262,20 +281,19 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
     for (int u = 0; u < BPT; ++u) {
         const int bi = threadIdx.x + u * T;
         const int c = bi / LR, j = bi % LR, k = j % NS;
-        float2* col = lds + c * LSP;
-        const int base = (j / NS) * RAD * NS + k;
+        float2* dst = lds + c * LSP + pidx((j / NS) * RAD * NS + k);
 #pragma unroll
-        for (int r = 0; r < RAD; ++r) col[pidx(base + r * NS)] = v[u * RAD + r];
+        for (int r = 0; r < RAD; ++r) dst[pidx(r * NS)] = v[u * RAD + r];
     }
     __syncthreads();
 }
 
 template <int L, int C, int NS>
 struct Radix16Stages {
-    static __device__ __forceinline__ void run(float2* lds, const float2* __restrict__ tw)
+    static __device__ __forceinline__ void run(float2* lds, const float2* __restrict__ twst)
     {
-        fft_stage<L, C, 16, NS>(lds, tw);
-        Radix16Stages<L, C, NS * 16>::run(lds, tw);
+        fft_stage<L, C, 16, NS>(lds, twst);
+        Radix16Stages<L, C, NS * 16>::run(lds, twst);
     }
 };
 template <int L, int C>
@@ -284,11 +302,12 @@ struct Radix16Stages<L, C, L> {
 };
 
 template <int L, int C>
-__device__ __forceinline__ void fft_tile(float2* lds, const float2* __restrict__ tw)
+__device__ __forceinline__ void fft_tile(float2* lds, const float2* __restrict__ twst)
 {
     constexpr int LG = Log2<L>::value, R0 = (LG % 4) ? (1 << (LG % 4)) : 16;
-    fft_stage<L, C, R0, 1>(lds, tw);
-    Radix16Stages<L, C, R0>::run(lds, tw);
+    static_assert(L / 16 <= TWST_NS_MAX, "stage twiddle table too short");
+    fft_stage<L, C, R0, 1>(lds, twst);
+    Radix16Stages<L, C, R0>::run(lds, twst);
 }
 
 __device__ __forceinline__ float2 twiddle2(const float2* __restrict__ lo, const float2* __restrict__ hi, uint32_t q)
@@ -365,21 +384,28 @@ __device__ __forceinline__ int64_t source_from_poly(const DelayPoly& d, int64_t 
 // (n1 < R, s < S) sits at ((n1 / C1) S + s) C1 + n1 % C1.  Pass-1 workgroup w
 // reads columns n1 in [w C1, (w+1) C1) down all rows s; a delayed read lands
 // in the same or a neighbouring column a few rows away, so its loads stay
-// contiguous instead of touching one cache line per sample.
+// contiguous instead of touching one cache line per sample.  SERIES_PAD zero
+// samples follow the n samples: a read outside the series is sent there.
 template <int S, int C1>
-__device__ __forceinline__ int64_t tiled_sample(int64_t j, int lgR)
+__device__ __forceinline__ uint32_t tiled_index(uint32_t i, int lgR)
 {
-    const int64_t m = j >> 1;
-    const int64_t n1 = m & ((1ll << lgR) - 1), s = m >> lgR;
-    return ((((n1 / C1) * S + s) * C1 + (n1 % C1)) << 1) | (j & 1);
+    constexpr int LS = Log2<S>::value, LC = Log2<C1>::value;
+    const uint32_t n1 = (i >> 1) & ((1u << lgR) - 1), s = i >> (lgR + 1);
+    const uint32_t pt = ((n1 >> LC) << (LS + LC)) | (s << LC) | (n1 & (C1 - 1));
+    return (pt << 1) | (i & 1);
 }
 
+// Sample i of the resident series, or one of the zero samples after it when
+// i is outside [0, n).  The index is computed unconditionally and then
+// selected, so that the gather stays one basic block the scheduler can
+// reorder; the load uses a 32-bit byte offset from the series base.
 template <int S, int C1>
-__device__ __forceinline__ int tiled_sample32(int j, int lgR)
+__device__ __forceinline__ float load_sample(const float* __restrict__ x, int i, uint32_t n, int lgR)
 {
-    const int m = j >> 1;
-    const int n1 = m & ((1 << lgR) - 1), s = m >> lgR;
-    return ((((n1 / C1) * S + s) * C1 + (n1 % C1)) << 1) | (j & 1);
+    uint32_t t = tiled_index<S, C1>((uint32_t)i, lgR);
+    asm volatile("" : "+v"(t));
+    const uint32_t a = (uint32_t)i < n ? t : n;
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(x) + (a << 2));
 }
 
 // Pass-1 gather for templates whose delay polynomial would not meet the
@@ -396,14 +422,13 @@ __device__ __attribute__((noinline)) void gather_exact(const float* __restrict__
     for (int e = threadIdx.x; e < C1 * S; e += T) {
         const int j = 2 * (c0 + (e % C1) + R * (e / C1));
         const int i0 = (int)source_index(p, j, tsamp), i1 = (int)source_index(p, j + 1, tsamp);
-        const bool ok0 = (unsigned)i0 < (unsigned)n, ok1 = (unsigned)i1 < (unsigned)n;
-        const float y0 = ok0 ? x[tiled_sample32<S, C1>(i0, lgR)] : 0.0f;
-        const float y1 = ok1 ? x[tiled_sample32<S, C1>(i1, lgR)] : 0.0f;
+        const uint32_t a0 = (unsigned)i0 < (unsigned)n ? tiled_index<S, C1>(i0, lgR) : (uint32_t)n;
+        const uint32_t a1 = (unsigned)i1 < (unsigned)n ? tiled_index<S, C1>(i1, lgR) : (uint32_t)n;
         if (src_out) {
             src_out[j] = i0;
             src_out[j + 1] = i1;
         }
-        lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(y0, y1);
+        lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(x[a0], x[a1]);
     }
 }
 
@@ -417,86 +442,121 @@ __global__ __launch_bounds__(NT) void k_tile_series(const float* __restrict__ in
     }
 }
 
+// Delay polynomials of a template, shared by every pass-1 workgroup.  Tile
+// points are grouped in chunks of 16 consecutive points e (row s = e / C1,
+// column c = e % C1); in the tile of column offset c0, point e carries the
+// samples j = 2 (c0 + c + R s) and j + 1.  Chunk g is expanded around the
+// middle sample jmid of its samples in the tile with c0 = 0; a tile with
+// another offset evaluates the same polynomial at u = j - jmid, at most
+// 2 (R - C1) further out, and the accuracy bound covers that full reach.
+// Every chunk spans the same samples, so one flag per template says whether
+// the polynomials are used or the exact per-sample solve.
+__global__ __launch_bounds__(NT) void k_chunk_polys(const TmplDev* __restrict__ tm, double tsamp, int R, int C1,
+                                                    int nchunk, ChunkPoly* __restrict__ polys, size_t poly_stride,
+                                                    int32_t* __restrict__ pok)
+{
+    const int g = (int)(blockIdx.x * NT + threadIdx.x);
+    const TmplDev p = tm[blockIdx.y];
+    auto jof = [&](int e) -> int { return 2 * (e % C1 + R * (e / C1)); };
+    if (g == 0) {
+        const int lo = jof(0), hi = jof(15) + 1, mid = lo + (hi - lo) / 2;
+        const double U = (double)(hi - mid) + 2.0 * (double)(R - C1);
+        pok[blockIdx.y] = poly_ok(p, tsamp, U) ? 1 : 0;
+    }
+    if (g >= nchunk) return;
+    const int lo = jof(16 * g), hi = jof(16 * g + 15) + 1, mid = lo + (hi - lo) / 2;
+    const DelayPoly d = delay_poly(p, tsamp, mid);
+    ChunkPoly c;
+    c.c0 = d.c0;
+    c.c1 = d.c1;
+    c.c2 = d.c2;
+    c.c3 = d.c3;
+    c.c4 = d.c4;
+    c.jmid = mid;
+    c.pad = 0;
+    polys[blockIdx.y * poly_stride + g] = c;
+}
+
 // ------------------------------------------------------------------------
 // Pass 1: for complex point m = n1 + R*n2 (n1 < R, n2 < S) the packed value
 // z_m = y_{2m} + i y_{2m+1} of the demodulated series, y_j = x0[src_j], is
 // gathered straight from the resident series; S-point transforms over n2;
 // the inter-pass twiddle W_M^{n1 k2}.  Workgroup w owns columns
 // n1 in [w C1, (w+1) C1) and writes them as the contiguous block Y[w][k2][c].
+// Thread t handles points e = t + T i (i < 16): column t % C1, row
+// t / C1 + (S/16) i, so a wave's loads are consecutive rows.
 template <int S, int C1>
 __global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ x, int64_t n, int R, int lgR,
                                                       double tsamp, const TmplDev* __restrict__ tm,
+                                                      const ChunkPoly* __restrict__ polys, size_t poly_stride,
+                                                      const int32_t* __restrict__ pok,
                                                       float2* __restrict__ Y, size_t y_stride,
-                                                      const float2* __restrict__ twS,
+                                                      const float2* __restrict__ twst,
                                                       const float2* __restrict__ twM_lo,
                                                       const float2* __restrict__ twM_hi, int32_t* __restrict__ src_out)
 {
-    constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1;
-    __shared__ float2 lds[C1 * LSP];
-    const TmplDev p = tm[blockIdx.y];
+    constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1, RS = S / 16;
+    __shared__ __align__(16) float2 lds[C1 * LSP];
+    static_assert(sizeof(ChunkPoly) * T <= sizeof(float2) * C1 * LSP, "polynomials must fit in the tile");
     const int tile = xcd_remap(blockIdx.x, R / C1);
     const int c0 = tile * C1;
+    const int c = (int)threadIdx.x % C1, row0 = (int)threadIdx.x / C1;
+    const uint32_t n32 = (uint32_t)n;
 
-    // Tile points are grouped in chunks of 16 consecutive points e (row
-    // s = e / C1, column c = e % C1, samples j(e) = 2 (c0 + c + R s) and
-    // j(e) + 1); every chunk spans the same number of samples, so whether the
-    // delay polynomial is accurate enough is decided once per workgroup.
-    // Phase A: thread t expands the delay of chunk t around the chunk's middle
-    // sample and parks the polynomial in the (still unused) tile memory.
-    // Phase B: each thread gathers points t + T i, so that a wave's loads are
-    // consecutive rows, issuing all 32 loads before using them.  Phase C: the
-    // gathered points go to the tile.  Sample indices fit in 32 bits (n <= 2^24
-    // and the host bounds the delay).
-    auto jof = [&](int e) -> int { return 2 * (c0 + (e % C1) + R * (e / C1)); };
-    auto jmid = [&](int g) -> int {
-        const int jlo = jof(16 * g), jhi = jof(16 * g + 15) + 1;
-        return jlo + (jhi - jlo) / 2;
-    };
-    const int n32 = (int)n;
-    const int half_span = jof(15) + 1 - jmid(0);
-    if (poly_ok(p, tsamp, (double)half_span)) {
-        DelayPoly* polys = reinterpret_cast<DelayPoly*>(lds);  // T x 40 B, inside the tile
-        polys[threadIdx.x] = delay_poly(p, tsamp, jmid((int)threadIdx.x));
+    if (pok[blockIdx.y]) {
+        // Sample indices fit in 32 bits: n <= 2^24 and the host bounds the delay.
+        // The template's T chunk polynomials are parked in the (not yet used)
+        // tile memory, so that their reads wait on LDS only and the series
+        // loads of earlier points stay in flight.
+        ChunkPoly* cp = reinterpret_cast<ChunkPoly*>(lds);
+        cp[threadIdx.x] = polys[blockIdx.y * poly_stride + threadIdx.x];
         __syncthreads();
+        auto sources = [&](int i, int& j, int& i0, int& i1) {
+            const ChunkPoly d = cp[((int)threadIdx.x + i * T) >> 4];
+            j = 2 * (c0 + c + R * (row0 + RS * i));
+            const double u = (double)(j - d.jmid), u1 = u + 1.0;
+            const double d0 = d.c0 + u * (d.c1 + u * (d.c2 + u * (d.c3 + u * d.c4)));
+            const double d1 = d.c0 + u1 * (d.c1 + u1 * (d.c2 + u1 * (d.c3 + u1 * d.c4)));
+            i0 = j - rint_i32(d0);
+            i1 = j + 1 - rint_i32(d1);
+        };
         float v[32];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int e = (int)threadIdx.x + i * T;
-            const int g = e >> 4;
-            const DelayPoly dp = polys[g];
-            const int j = jof(e);
-            const double u = (double)(j - jmid(g));
-            const double d0 = dp.c0 + u * (dp.c1 + u * (dp.c2 + u * (dp.c3 + u * dp.c4)));
-            const double u1 = u + 1.0;
-            const double d1 = dp.c0 + u1 * (dp.c1 + u1 * (dp.c2 + u1 * (dp.c3 + u1 * dp.c4)));
-            const int i0 = j - (int)rint(d0), i1 = j + 1 - (int)rint(d1);
-            const bool ok0 = (unsigned)i0 < (unsigned)n32, ok1 = (unsigned)i1 < (unsigned)n32;
-            const float y0 = x[tiled_sample32<S, C1>(ok0 ? i0 : 0, lgR)];
-            const float y1 = x[tiled_sample32<S, C1>(ok1 ? i1 : 0, lgR)];
-            v[2 * i] = ok0 ? y0 : 0.0f;
-            v[2 * i + 1] = ok1 ? y1 : 0.0f;
-            if (src_out) {
+            int j, i0, i1;
+            sources(i, j, i0, i1);
+            v[2 * i] = load_sample<S, C1>(x, i0, n32, lgR);
+            v[2 * i + 1] = load_sample<S, C1>(x, i1, n32, lgR);
+        }
+        if (src_out) {
+            for (int i = 0; i < 16; ++i) {
+                int j, i0, i1;
+                sources(i, j, i0, i1);
                 src_out[j] = i0;
                 src_out[j + 1] = i1;
             }
         }
         __syncthreads();
+        float2* dst = lds + c * LSP + pidx(row0);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int e = (int)threadIdx.x + i * T;
-            lds[(e % C1) * LSP + pidx(e / C1)] = make_float2(v[2 * i], v[2 * i + 1]);
-        }
+        for (int i = 0; i < 16; ++i) dst[pidx(RS * i)] = make_float2(v[2 * i], v[2 * i + 1]);
     } else {
-        gather_exact<S, C1>(x, n32, c0, R, lgR, tsamp, tm + blockIdx.y, lds, src_out);
+        gather_exact<S, C1>(x, (int)n32, c0, R, lgR, tsamp, tm + blockIdx.y, lds, src_out);
     }
     __syncthreads();
-    fft_tile<S, C1>(lds, twS);
+    fft_tile<S, C1>(lds, twst);
 
-    float2* out = Y + blockIdx.y * y_stride + (size_t)tile * S * C1;
-    for (int e = threadIdx.x; e < C1 * S; e += T) {
-        const int k2 = e / C1, c = e % C1;
-        const uint32_t q = (uint32_t)(c0 + c) * (uint32_t)k2;
-        out[e] = cmul(lds[c * LSP + pidx(k2)], twiddle2(twM_lo, twM_hi, q));
+    // W_M^{(c0+c) k2} for k2 = row0 + RS i: start value times W_M^{(c0+c) RS}
+    // per step (a recurrence of at most 15 products).
+    float2* out = Y + blockIdx.y * y_stride + (size_t)tile * S * C1 + threadIdx.x;
+    const uint32_t col = (uint32_t)(c0 + c);
+    float2 w = twiddle2(twM_lo, twM_hi, col * (uint32_t)row0);
+    const float2 z = twiddle2(twM_lo, twM_hi, col * (uint32_t)RS);
+    const float2* src = lds + c * LSP + pidx(row0);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        out[i * T] = cmul(src[pidx(RS * i)], w);
+        w = cmul(w, z);
     }
 }
 
@@ -520,11 +580,11 @@ __device__ __forceinline__ float power_of(float2 z, float2 zm, float2 w)
 template <int R, int D2>
 __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__ Y, size_t y_stride, int S, int C1,
                                                       float* __restrict__ P, size_t p_stride, int64_t M,
-                                                      const float2* __restrict__ twR,
+                                                      const float2* __restrict__ twst,
                                                       const float2* __restrict__ tw2M_lo,
                                                       const float2* __restrict__ tw2M_hi)
 {
-    constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2;
+    constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2, RK = R / 16;
     __shared__ float2 lds[D2 * LSP];
     const int g = xcd_remap(blockIdx.x, S / D2);
     const float2* Ys = Y + blockIdx.y * y_stride;
@@ -551,27 +611,36 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
         lds[q * LSP + pidx(w * C1 + c)] = v[i];
     }
     __syncthreads();
-    fft_tile<R, D2>(lds, twR);
+    fft_tile<R, D2>(lds, twst);
 
-    for (int e = threadIdx.x; e < D2 * R; e += T) {
-        const int q = e % D2, k1 = e / D2;
-        const int a = g * D + (q < D ? q : q - D);
-        int col, pq, pk;
-        if (q < D) {
-            col = a;
-            pq = (a == 0) ? q : q + D;
-            pk = (a == 0) ? ((R - k1) & (R - 1)) : R - 1 - k1;
-        } else {
-            col = (a == 0) ? S / 2 : S - a;
-            pq = (a == 0) ? q : q - D;
-            pk = R - 1 - k1;
-        }
-        const float2 z = lds[q * LSP + pidx(k1)];
-        const float2 zm = lds[pq * LSP + pidx(pk)];
+    // Thread t emits slot q = t % D2 at k1 = t / D2 + RK i.  The split twiddle
+    // W_2M^{col + S k1} advances by W_2M^{S RK} = W_32 per step.
+    const int q = (int)threadIdx.x % D2, k1t = (int)threadIdx.x / D2;
+    const int a = g * D + (q < D ? q : q - D);
+    int col, pq;
+    if (q < D) {
+        col = a;
+        pq = (a == 0) ? q : q + D;
+    } else {
+        col = (a == 0) ? S / 2 : S - a;
+        pq = (a == 0) ? q : q - D;
+    }
+    const bool self = q < D && a == 0;  // column 0: Z_{M-k} at k1' = (R - k1) mod R
+    float2 w = twiddle2(tw2M_lo, tw2M_hi, (uint32_t)col + (uint32_t)S * (uint32_t)k1t);
+    const float2 z = make_float2(0.98078528040323044913f, -0.19509032201612826785f);
+    const float2* own = lds + q * LSP;
+    const float2* mir = lds + pq * LSP;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int k1 = k1t + RK * i;
+        const int pk = self ? ((R - k1) & (R - 1)) : R - 1 - k1;
+        const float2 zo = own[pidx(k1)];
+        const float2 zm = mir[pidx(pk)];
         const uint32_t k = (uint32_t)col + (uint32_t)S * (uint32_t)k1;
-        Ps[k] = power_of(z, zm, twiddle2(tw2M_lo, tw2M_hi, k));
-        if (q == 0 && a == 0 && k1 == 0) {
-            const float sm = z.x - z.y;
+        Ps[k] = power_of(zo, zm, w);
+        w = cmul(w, z);
+        if (i == 0 && self && k1 == 0) {
+            const float sm = zo.x - zo.y;
             Ps[M] = sm * sm;
         }
     }
@@ -581,15 +650,16 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
 // Whitening block medians: element of rank floor((n_b-1)/2) of bins
 // [1 + bW, 1 + bW + n_b), by radix selection on the IEEE bits (powers are
 // non-negative, so unsigned order is numeric order).  Digits: the 8 exponent
-// bits, then 8, 8 and 7 mantissa bits.  Counting uses LDS atomics into four
-// histogram copies per wave (lane & 3) to thin out collisions on the few
-// exponent values a block spans; the digit holding the rank is found with a
-// block-wide prefix sum.
+// bits, then 8, 8 and 7 mantissa bits.  The block's values stay in registers
+// (VPT per thread).  Counting uses LDS atomics into two histogram copies per
+// wave (lane & 1) to thin out collisions on the few exponents a block spans;
+// the digit holding the rank is found with a block-wide prefix sum, and each
+// thread clears the bins it has read for the next digit.
+template <int VPT>
 __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size_t p_stride, int64_t M, int W,
                                                float* __restrict__ med, size_t med_stride)
 {
-    constexpr int NW = NT / 64, NC = 4;
-    extern __shared__ uint32_t vals[];
+    constexpr int NW = NT / 64, NC = 2;
     __shared__ uint32_t hist[NW * NC][256];
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_digit, s_rank;
@@ -598,24 +668,34 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
     const float* Ps = P + blockIdx.y * p_stride;
     const int64_t start = 1 + (int64_t)b * W;
     const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
-    for (int i = threadIdx.x; i < cnt; i += NT) vals[i] = __float_as_uint(Ps[start + i]);
+    uint32_t v[VPT];
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        const int q = (int)threadIdx.x + i * NT;
+        // absent entries get the largest key and never match a prefix of a real one
+        v[i] = q < cnt ? __float_as_uint(Ps[start + q]) : 0xffffffffu;
+    }
+#pragma unroll
+    for (int i = 0; i < NW * NC; ++i) hist[i][threadIdx.x] = 0;
+    __syncthreads();
     uint32_t* myhist = hist[wave * NC + (lane & (NC - 1))];
     uint32_t rank = (uint32_t)(cnt - 1) / 2, prefix = 0, mask = 0;
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
         const int shift = pass == 0 ? 23 : pass == 1 ? 15 : pass == 2 ? 7 : 0;
         const uint32_t dmask = pass == 3 ? 127u : 255u;
-        for (int i = threadIdx.x; i < NW * NC * 256; i += NT) (&hist[0][0])[i] = 0;
+        const uint32_t m2 = mask | 0x80000000u;  // keys >= 2^31 (absent entries) never match
+#pragma unroll
+        for (int i = 0; i < VPT; ++i)
+            if ((v[i] & m2) == prefix) atomicAdd(&myhist[(v[i] >> shift) & dmask], 1u);
         __syncthreads();
-        for (int i = threadIdx.x; i < cnt; i += NT) {
-            const uint32_t v = vals[i];
-            if ((v & mask) == prefix) atomicAdd(&myhist[(v >> shift) & dmask], 1u);
-        }
-        __syncthreads();
-        // thread t owns digit t (NT == 256)
+        // thread t owns digit t (NT == 256); it reads and clears that bin
         uint32_t tot = 0;
 #pragma unroll
-        for (int w = 0; w < NW * NC; ++w) tot += hist[w][threadIdx.x];
+        for (int w = 0; w < NW * NC; ++w) {
+            tot += hist[w][threadIdx.x];
+            hist[w][threadIdx.x] = 0;
+        }
         uint32_t inc = tot;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -625,7 +705,9 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
         if (lane == 63) wsum[wave] = inc;
         __syncthreads();
         uint32_t before = 0;
-        for (int w = 0; w < wave; ++w) before += wsum[w];
+#pragma unroll
+        for (int w = 0; w < NW; ++w)
+            if (w < wave) before += wsum[w];
         const uint32_t excl = before + inc - tot;
         if (tot && excl <= rank && rank < excl + tot) {
             s_digit = threadIdx.x;
@@ -635,7 +717,6 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
         prefix |= s_digit << shift;
         mask |= dmask << shift;
         rank = s_rank;
-        __syncthreads();
     }
     if (threadIdx.x == 0) med[blockIdx.y * med_stride + b] = __uint_as_float(prefix);
 }
@@ -849,8 +930,8 @@ hipError_t fft1_launch(const Geometry& g, const float* x, double tsamp, const Tm
                        const Slots& ws, int32_t* src_out, hipStream_t s)
 {
     dim3 grid(g.R / C1, nslots);
-    hipLaunchKernelGGL((k_fft1<S, C1>), grid, dim3(C1 * S / 16), 0, s, x, g.n, g.R, g.lgR, tsamp, tm, ws.Y,
-                       ws.y_stride, g.twS, g.twM_lo, g.twM_hi, src_out);
+    hipLaunchKernelGGL((k_fft1<S, C1>), grid, dim3(C1 * S / 16), 0, s, x, g.n, g.R, g.lgR, tsamp, tm, ws.poly,
+                       ws.poly_stride, ws.pok, ws.Y, ws.y_stride, g.twst, g.twM_lo, g.twM_hi, src_out);
     return hipGetLastError();
 }
 
@@ -859,8 +940,51 @@ hipError_t fft2_launch(const Geometry& g, int nslots, const Slots& ws, hipStream
 {
     dim3 grid(g.S / D2, nslots);
     hipLaunchKernelGGL((k_fft2<R, D2>), grid, dim3(D2 * R / 16), 0, s, ws.Y, ws.y_stride, g.S, g.C1, ws.P,
-                       ws.p_stride, g.M, g.twR, g.tw2M_lo, g.tw2M_hi);
+                       ws.p_stride, g.M, g.twst, g.tw2M_lo, g.tw2M_hi);
     return hipGetLastError();
+}
+
+template <int A, int B>
+struct Shape {
+    static constexpr int a = A, b = B;
+};
+
+// Pass-1 shapes (S, C1) and pass-2 shapes (R, D2) of the 16384- and
+// 8192-point tiles, n = 2^10 .. 2^24.
+template <class... K>
+hipError_t fft1_dispatch(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int nslots,
+                         const Slots& ws, int32_t* src_out, hipStream_t s)
+{
+    hipError_t e = hipErrorInvalidValue;
+    (void)((g.S == K::a && g.C1 == K::b ? (e = fft1_launch<K::a, K::b>(g, x, tsamp, tm, nslots, ws, src_out, s),
+                                           true)
+                                        : false) ||
+           ...);
+    return e;
+}
+template <class... K>
+hipError_t fft2_dispatch(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
+{
+    hipError_t e = hipErrorInvalidValue;
+    (void)((g.R == K::a && g.D2 == K::b ? (e = fft2_launch<K::a, K::b>(g, nslots, ws, s), true) : false) || ...);
+    return e;
+}
+
+hipError_t launch_fft1(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int nslots,
+                       const Slots& ws, int32_t* src_out, hipStream_t s)
+{
+    return fft1_dispatch<Shape<32, 16>, Shape<64, 16>, Shape<128, 16>, Shape<256, 16>, Shape<512, 16>,
+                         Shape<1024, 16>, Shape<1024, 8>, Shape<2048, 8>, Shape<2048, 4>, Shape<4096, 4>,
+                         Shape<4096, 2>, Shape<8192, 2>, Shape<8192, 1>, Shape<16384, 1>>(g, x, tsamp, tm, nslots,
+                                                                                         ws, src_out, s);
+}
+
+hipError_t launch_fft2(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
+{
+    return fft2_dispatch<Shape<16, 32>, Shape<16, 64>, Shape<16, 128>, Shape<16, 256>, Shape<16, 512>,
+                         Shape<16, 1024>, Shape<32, 512>, Shape<64, 256>, Shape<128, 128>, Shape<256, 64>,
+                         Shape<512, 32>, Shape<32, 256>, Shape<64, 128>, Shape<128, 64>, Shape<256, 32>,
+                         Shape<512, 16>, Shape<1024, 8>>(g, nslots, ws, s);
 }
 
 }  // namespace
@@ -915,43 +1039,24 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
     hipError_t e;
     const TmplDev* tmw = tm + tmpl_base;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
-    switch (g.S * 32 + g.C1) {
-    case 32 * 32 + 16: e = fft1_launch<32, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 64 * 32 + 16: e = fft1_launch<64, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 128 * 32 + 16: e = fft1_launch<128, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 256 * 32 + 16: e = fft1_launch<256, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 512 * 32 + 16: e = fft1_launch<512, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 1024 * 32 + 16: e = fft1_launch<1024, 16>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 2048 * 32 + 8: e = fft1_launch<2048, 8>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 4096 * 32 + 4: e = fft1_launch<4096, 4>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 8192 * 32 + 2: e = fft1_launch<8192, 2>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    case 16384 * 32 + 1: e = fft1_launch<16384, 1>(g, x, tsamp, tmw, nslots, ws, ins.src, s); break;
-    default: return hipErrorInvalidValue;
-    }
-    if (e != hipSuccess) return e;
+    const int nchunk = (int)(std::min<int64_t>(g.TE, g.M) / 16);
+    hipLaunchKernelGGL(k_chunk_polys, dim3((nchunk + NT - 1) / NT, nslots), dim3(NT), 0, s, tmw, tsamp, g.R, g.C1,
+                       nchunk, ws.poly, ws.poly_stride, ws.pok);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_fft1(g, x, tsamp, tmw, nslots, ws, ins.src, s)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    switch (g.R * 4096 + g.D2) {
-    case 16 * 4096 + 32: e = fft2_launch<16, 32>(g, nslots, ws, s); break;
-    case 16 * 4096 + 64: e = fft2_launch<16, 64>(g, nslots, ws, s); break;
-    case 16 * 4096 + 128: e = fft2_launch<16, 128>(g, nslots, ws, s); break;
-    case 16 * 4096 + 256: e = fft2_launch<16, 256>(g, nslots, ws, s); break;
-    case 16 * 4096 + 512: e = fft2_launch<16, 512>(g, nslots, ws, s); break;
-    case 16 * 4096 + 1024: e = fft2_launch<16, 1024>(g, nslots, ws, s); break;
-    case 32 * 4096 + 512: e = fft2_launch<32, 512>(g, nslots, ws, s); break;
-    case 64 * 4096 + 256: e = fft2_launch<64, 256>(g, nslots, ws, s); break;
-    case 128 * 4096 + 128: e = fft2_launch<128, 128>(g, nslots, ws, s); break;
-    case 256 * 4096 + 64: e = fft2_launch<256, 64>(g, nslots, ws, s); break;
-    case 512 * 4096 + 32: e = fft2_launch<512, 32>(g, nslots, ws, s); break;
-    default: return hipErrorInvalidValue;
-    }
-    if (e != hipSuccess) return e;
+    if ((e = launch_fft2(g, nslots, ws, s)) != hipSuccess) return e;
     if (ins.power &&
         (e = hipMemcpyAsync(ins.power, ws.P, sizeof(float) * (size_t)(g.M + 1), hipMemcpyDeviceToDevice, s)) !=
             hipSuccess)
         return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_median, dim3(g.nblk, nslots), dim3(NT), sizeof(uint32_t) * (size_t)g.W, s, ws.P,
-                       ws.p_stride, g.M, g.W, ws.med, ws.med_stride);
+    if (g.W <= 16 * NT)
+        hipLaunchKernelGGL((k_median<16>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
+                           ws.med, ws.med_stride);
+    else
+        hipLaunchKernelGGL((k_median<32>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
+                           ws.med, ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk, ws.med,
