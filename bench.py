@@ -177,7 +177,8 @@ def run_bank(args, tb, torch):
     w = workload(args.workload, args.templates)
     conf = describe(w, args.workload)
     conf["tile_points"] = args.tile or DEFAULT_TILE
-    lanes = args.lanes or (4 if len(w.series) > 1 else 1)
+    conf["requests_per_series"] = max(1, args.split)
+    lanes = args.lanes or (4 if len(w.series) > 1 else max(1, args.split))
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
                    threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18,
                    tile_points=args.tile)
@@ -185,8 +186,10 @@ def run_bank(args, tb, torch):
     ntemp = len(w.templates)
     nitems = ntemp * len(sids)
 
+    chunks = np.array_split(np.arange(ntemp), max(1, args.split))
+
     def step():
-        rids = [plan.submit(sid, w.templates) for sid in sids]
+        rids = [plan.submit(sid, w.templates[c[0]:c[-1] + 1], int(c[0])) for sid in sids for c in chunks if len(c)]
         ncand = 0
         for rid in rids:
             c, tot = plan.candidates(rid)
@@ -301,6 +304,7 @@ def main():
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--batch", type=int, default=0, help="templates in flight per launch (0 = library default)")
     ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--split", type=int, default=1, help="requests the bank is cut into per series (spread over lanes)")
     ap.add_argument("--tile", type=int, default=0, help="FFT points per workgroup, 8192 or 16384 (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -140,9 +140,11 @@ struct Lane {
 };
 
 struct Req {
-    int lane = 0;
+    int lane = 0;         // primary lane: request memory and the completion event live on its stream
     double work = 0;      // templates x samples, for lane balancing
-    bool settled = false; // completion already subtracted from the lane's pending work
+    bool settled = false; // completion already subtracted from the lanes' pending work
+    std::vector<std::pair<int, double>> parts;  // (lane, work) of every lane the waves run on
+    std::vector<hipEvent_t> joins;              // primary ready / helper lanes done
     int32_t series = -1;
     uint32_t count = 0, first = 0;
     uint64_t cap = 0;
@@ -360,6 +362,8 @@ void free_request(tb_plan_t p, Req& r)
 {
     if (r.ev0) hipEventDestroy(r.ev0);
     if (r.ev1) hipEventDestroy(r.ev1);
+    for (hipEvent_t e : r.joins) hipEventDestroy(e);
+    r.joins.clear();
     if (r.dmem) hipFreeAsync(r.dmem, p->lanes[r.lane].stream);
     hipHostFree(r.h_t);
     r.dmem = nullptr;
@@ -381,11 +385,21 @@ ReqLayout req_layout(uint32_t count, uint64_t cap)
     return L;
 }
 
-// Queue the kernels of all templates of a request, wave by wave.
-tb_status enqueue(tb_plan_t p, hipStream_t stream, const SeriesRec& sr, Geometry* g, Slots* ws, const TmplDev* d_tm,
+// Queue the kernels of all templates of a request, wave by wave; wave i goes
+// to workspace i mod (number of workspaces) on that workspace's stream.
+struct Crew {
+    std::vector<hipStream_t> streams;
+    std::vector<Slots*> slots;
+};
+
+tb_status enqueue(tb_plan_t p, const Crew& crew, const SeriesRec& sr, Geometry* g, const TmplDev* d_tm,
                   uint32_t count, const PeakParams& pp, uint4* ring, uint32_t* counter, const Inspect& ins)
 {
-    for (uint32_t w0 = 0; w0 < count; w0 += (uint32_t)ws->B) {
+    const size_t nc = crew.streams.size();
+    size_t wave = 0;
+    for (uint32_t w0 = 0; w0 < count; ++wave) {
+        Slots* ws = crew.slots[wave % nc];
+        hipStream_t stream = crew.streams[wave % nc];
         int nslots = (int)std::min<uint32_t>((uint32_t)ws->B, count - w0);
         hipEvent_t* ev = nullptr;
         if (p->profiling) {
@@ -399,6 +413,7 @@ tb_status enqueue(tb_plan_t p, hipStream_t stream, const SeriesRec& sr, Geometry
         if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, pp, ring, counter, ins, stream, ev) !=
             hipSuccess)
             return TB_ERR_DEVICE;
+        w0 += (uint32_t)nslots;
     }
     return TB_OK;
 }
@@ -409,7 +424,7 @@ void settle(tb_plan_t p)
     for (auto& kv : p->reqs) {
         Req& r = kv.second;
         if (!r.settled && hipEventQuery(r.ev1) == hipSuccess) {
-            p->lanes[r.lane].pending -= r.work;
+            for (auto& pw : r.parts) p->lanes[pw.first].pending -= pw.second;
             r.settled = true;
         }
     }
@@ -729,16 +744,59 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
         p->held -= r.bytes;
         return TB_ERR_DEVICE;
     }
-    Inspect none;
-    st = enqueue(p, stream, sr, g, ws, d_tm, count, pp, ring, counter, none);
-    if (st == TB_OK && hipEventRecord(r.ev1, stream) != hipSuccess) st = TB_ERR_DEVICE;
-    if (st) {
-        hipStreamSynchronize(stream);
+    // Idle lanes (no queued work) help with requests of more than one wave:
+    // they wait for the prepared templates, take every k-th wave on their own
+    // workspace, and the primary lane waits for them before the completion
+    // event.  All waves append to the request's one candidate ring.
+    Crew crew;
+    crew.streams.push_back(stream);
+    crew.slots.push_back(ws);
+    if (count > (uint32_t)ws->B) {
+        for (int l = 0; l < (int)p->lanes.size() && crew.streams.size() * (size_t)ws->B < count; ++l) {
+            Slots* hs = nullptr;
+            if (l == lane || p->lanes[l].pending > 0.0 || get_slots(p, l, *g, &hs) != TB_OK) continue;
+            crew.streams.push_back(p->lanes[l].stream);
+            crew.slots.push_back(hs);
+            r.parts.emplace_back(l, 0.0);
+        }
+    }
+    auto fail = [&](tb_status why) {
+        for (hipStream_t cs : crew.streams) hipStreamSynchronize(cs);
         free_request(p, r);
         p->held -= r.bytes;
-        return st;
+        return why;
+    };
+    if (crew.streams.size() > 1) {
+        hipEvent_t ready = nullptr;
+        if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return fail(TB_ERR_DEVICE);
+        r.joins.push_back(ready);
+        if (hipEventRecord(ready, stream) != hipSuccess) return fail(TB_ERR_DEVICE);
+        for (size_t c = 1; c < crew.streams.size(); ++c)
+            if (hipStreamWaitEvent(crew.streams[c], ready, 0) != hipSuccess) return fail(TB_ERR_DEVICE);
     }
-    p->lanes[lane].pending += r.work;
+    Inspect none;
+    st = enqueue(p, crew, sr, g, d_tm, count, pp, ring, counter, none);
+    if (st) return fail(st);
+    for (size_t c = 1; c < crew.streams.size(); ++c) {
+        hipEvent_t done = nullptr;
+        if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) return fail(TB_ERR_DEVICE);
+        r.joins.push_back(done);
+        if (hipEventRecord(done, crew.streams[c]) != hipSuccess || hipStreamWaitEvent(stream, done, 0) != hipSuccess)
+            return fail(TB_ERR_DEVICE);
+    }
+    if (hipEventRecord(r.ev1, stream) != hipSuccess) return fail(TB_ERR_DEVICE);
+    // pending work split by waves taken
+    {
+        const size_t nc = crew.streams.size(), nw = (count + (uint32_t)ws->B - 1) / (uint32_t)ws->B;
+        const double per_wave = nw ? r.work / (double)nw : 0.0;
+        std::vector<double> share(nc, 0.0);
+        for (size_t i = 0; i < nw; ++i) share[i % nc] += per_wave;
+        r.parts.insert(r.parts.begin(), std::make_pair(lane, 0.0));
+        for (size_t c = 0; c < nc; ++c) {
+            r.parts[c].second = share[c];
+            p->lanes[r.parts[c].first].pending += share[c];
+        }
+    }
     int64_t rid = p->next_req++;
     p->reqs.emplace(rid, std::move(r));
     *request_id = rid;
@@ -797,7 +855,8 @@ tb_status tb_release(tb_plan_t p, int64_t rid)
     if (it == p->reqs.end()) return TB_ERR_UNKNOWN_ID;
     TB_TRY(hipSetDevice(p->cfg.device));
     TB_TRY(hipEventSynchronize(it->second.ev1));
-    if (!it->second.settled) p->lanes[it->second.lane].pending -= it->second.work;
+    if (!it->second.settled)
+        for (auto& pw : it->second.parts) p->lanes[pw.first].pending -= pw.second;
     p->held -= it->second.bytes;
     free_request(p, it->second);
     p->reqs.erase(it);
@@ -949,7 +1008,10 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
         hipMemcpyAsync(d_t, ht, sizeof(tb_template), hipMemcpyHostToDevice, p->stream) != hipSuccess ||
         launch_template_prep(d_t, 1, d_tm, p->stream) != hipSuccess)
         st = TB_ERR_DEVICE;
-    if (!st) st = enqueue(p, p->stream, sr, g, ws, d_tm, 1, pp, ring, counter, ins);
+    Crew crew;
+    crew.streams.push_back(p->stream);
+    crew.slots.push_back(ws);
+    if (!st) st = enqueue(p, crew, sr, g, d_tm, 1, pp, ring, counter, ins);
     if (!st && hipStreamSynchronize(p->stream) != hipSuccess) st = TB_ERR_DEVICE;
     if (!st && src && hipMemcpy(src, ins.src, sizeof(int32_t) * (size_t)sr.n, hipMemcpyDeviceToHost) != hipSuccess)
         st = TB_ERR_DEVICE;

@@ -486,7 +486,7 @@ __global__ __launch_bounds__(NT) void k_chunk_polys(const TmplDev* __restrict__ 
 // Thread t handles points e = t + T i (i < 16): column t % C1, row
 // t / C1 + (S/16) i, so a wave's loads are consecutive rows.
 template <int S, int C1>
-__global__ __launch_bounds__(C1 * S / 16) void k_fft1(const float* __restrict__ x, int64_t n, int R, int lgR,
+__global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict__ x, int64_t n, int R, int lgR,
                                                       double tsamp, const TmplDev* __restrict__ tm,
                                                       const ChunkPoly* __restrict__ polys, size_t poly_stride,
                                                       const int32_t* __restrict__ pok,
@@ -578,38 +578,34 @@ __device__ __forceinline__ float power_of(float2 z, float2 zm, float2 w)
 // (in column 0 at (R - k1) mod R).  Each slot emits |X|^2 for its own bins:
 // runs of D consecutive bins per k1, ascending for A, descending for mirrors.
 template <int R, int D2>
-__global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__ Y, size_t y_stride, int S, int C1,
-                                                      float* __restrict__ P, size_t p_stride, int64_t M,
+__global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__ Y, size_t y_stride, int S, int lgS,
+                                                      int lgC1, float* __restrict__ P, size_t p_stride, int64_t M,
                                                       const float2* __restrict__ twst,
                                                       const float2* __restrict__ tw2M_lo,
                                                       const float2* __restrict__ tw2M_hi)
 {
-    constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2, RK = R / 16;
+    constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2, RK = R / 16, LD2 = Log2<D2>::value;
     __shared__ float2 lds[D2 * LSP];
     const int g = xcd_remap(blockIdx.x, S / D2);
     const float2* Ys = Y + blockIdx.y * y_stride;
     float* Ps = P + blockIdx.y * p_stride;
+    const int cmask = (1 << lgC1) - 1;
 
+    // element e = (w, q, c): block w of pass 1, slot q, column c (C1 = 2^lgC1)
     float2 v[16];
+    int laddr[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int e = (int)threadIdx.x + i * T;
-        const int c = e % C1, q = (e / C1) % D2, w = e / (C1 * D2);
-        int col;
-        if (q < D) {
-            col = g * D + q;
-        } else {
-            const int a = g * D + (q - D);
-            col = (a == 0) ? S / 2 : S - a;
-        }
-        v[i] = Ys[((size_t)w * S + col) * C1 + c];
+        const int c = e & cmask, q = (e >> lgC1) & (D2 - 1), w = e >> (lgC1 + LD2);
+        const int a = g * D + (q < D ? q : q - D);
+        const int col = q < D ? a : (a == 0 ? S / 2 : S - a);
+        const uint32_t src = ((((uint32_t)w << lgS) + (uint32_t)col) << lgC1) | (uint32_t)c;
+        v[i] = Ys[src];
+        laddr[i] = q * LSP + pidx((w << lgC1) | c);
     }
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = (int)threadIdx.x + i * T;
-        const int c = e % C1, q = (e / C1) % D2, w = e / (C1 * D2);
-        lds[q * LSP + pidx(w * C1 + c)] = v[i];
-    }
+    for (int i = 0; i < 16; ++i) lds[laddr[i]] = v[i];
     __syncthreads();
     fft_tile<R, D2>(lds, twst);
 
@@ -649,18 +645,19 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
 // ------------------------------------------------------------------------
 // Whitening block medians: element of rank floor((n_b-1)/2) of bins
 // [1 + bW, 1 + bW + n_b), by radix selection on the IEEE bits (powers are
-// non-negative, so unsigned order is numeric order).  Digits: the 8 exponent
-// bits, then 8, 8 and 7 mantissa bits.  The block's values stay in registers
-// (VPT per thread).  Counting uses LDS atomics into two histogram copies per
-// wave (lane & 1) to thin out collisions on the few exponents a block spans;
-// the digit holding the rank is found with a block-wide prefix sum, and each
-// thread clears the bins it has read for the next digit.
+// non-negative, so unsigned order is numeric order).  Three digits: bits
+// 30..20 (the exponent and three mantissa bits, so that the few exponents a
+// block spans spread over many histogram bins), then 19..10 and 9..0.  The
+// block's values stay in registers (VPT per thread).  Counting uses LDS
+// atomics into two histogram copies (wave parity); thread t owns the
+// NBIN/NT consecutive bins from t NBIN/NT on, sums and clears them, and a
+// block-wide prefix sum over the threads finds the digit holding the rank.
 template <int VPT>
 __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size_t p_stride, int64_t M, int W,
                                                float* __restrict__ med, size_t med_stride)
 {
-    constexpr int NW = NT / 64, NC = 2;
-    __shared__ uint32_t hist[NW * NC][256];
+    constexpr int NW = NT / 64, NC = 2, NB0 = 2048;
+    __shared__ uint32_t hist[NC][NB0];
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_digit, s_rank;
     const int b = blockIdx.x;
@@ -676,25 +673,34 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
         v[i] = q < cnt ? __float_as_uint(Ps[start + q]) : 0xffffffffu;
     }
 #pragma unroll
-    for (int i = 0; i < NW * NC; ++i) hist[i][threadIdx.x] = 0;
+    for (int i = 0; i < NC * NB0 / NT; ++i) (&hist[0][0])[threadIdx.x + i * NT] = 0;
     __syncthreads();
-    uint32_t* myhist = hist[wave * NC + (lane & (NC - 1))];
-    uint32_t rank = (uint32_t)(cnt - 1) / 2, prefix = 0, mask = 0;
+    uint32_t* myhist = hist[wave & (NC - 1)];
+    uint32_t rank = (uint32_t)(cnt - 1) / 2, prefix = 0, mask = 0x80000000u;
 #pragma unroll
-    for (int pass = 0; pass < 4; ++pass) {
-        const int shift = pass == 0 ? 23 : pass == 1 ? 15 : pass == 2 ? 7 : 0;
-        const uint32_t dmask = pass == 3 ? 127u : 255u;
-        const uint32_t m2 = mask | 0x80000000u;  // keys >= 2^31 (absent entries) never match
+    for (int pass = 0; pass < 3; ++pass) {
+        const int shift = pass == 0 ? 20 : pass == 1 ? 10 : 0;
+        const int nbin = pass == 0 ? 2048 : 1024;
+        const uint32_t dmask = (uint32_t)nbin - 1;
+        const int per = nbin / NT;  // bins per thread: 8, then 4
 #pragma unroll
         for (int i = 0; i < VPT; ++i)
-            if ((v[i] & m2) == prefix) atomicAdd(&myhist[(v[i] >> shift) & dmask], 1u);
+            if ((v[i] & mask) == prefix) atomicAdd(&myhist[(v[i] >> shift) & dmask], 1u);
         __syncthreads();
-        // thread t owns digit t (NT == 256); it reads and clears that bin
+        uint32_t cnts[8];
         uint32_t tot = 0;
 #pragma unroll
-        for (int w = 0; w < NW * NC; ++w) {
-            tot += hist[w][threadIdx.x];
-            hist[w][threadIdx.x] = 0;
+        for (int k = 0; k < 8; ++k) {
+            cnts[k] = 0;
+            if (k < per) {
+                const int bin = (int)threadIdx.x * per + k;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    cnts[k] += hist[c][bin];
+                    hist[c][bin] = 0;
+                }
+                tot += cnts[k];
+            }
         }
         uint32_t inc = tot;
 #pragma unroll
@@ -704,14 +710,20 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
         }
         if (lane == 63) wsum[wave] = inc;
         __syncthreads();
-        uint32_t before = 0;
+        uint32_t excl = inc - tot;
 #pragma unroll
         for (int w = 0; w < NW; ++w)
-            if (w < wave) before += wsum[w];
-        const uint32_t excl = before + inc - tot;
-        if (tot && excl <= rank && rank < excl + tot) {
-            s_digit = threadIdx.x;
-            s_rank = rank - excl;
+            if (w < wave) excl += wsum[w];
+        if (excl <= rank && rank < excl + tot) {
+            uint32_t run = excl;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                if (k < per && cnts[k] && run <= rank && rank < run + cnts[k]) {
+                    s_digit = (uint32_t)((int)threadIdx.x * per + k);
+                    s_rank = rank - run;
+                }
+                run += cnts[k];
+            }
         }
         __syncthreads();
         prefix |= s_digit << shift;
@@ -724,38 +736,41 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
 // Whitening: P^_k = P_k ln2 / m(k), m the straight line between neighbouring
 // block-median centres c_b = start_b + (n_b - 1)/2, held constant before the
 // first and after the last centre; P^_0 = 0.  One workgroup per block, in
-// place.  Centres are kept doubled so that they stay integers.
+// place.  Centres are kept doubled so that they stay integers (below 2^24, so
+// exact in FP32); the line is evaluated as m_left + slope (2q - 2c_left).
 __global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_stride, int64_t M, int W, int nblk,
                                                const float* __restrict__ med, size_t med_stride)
 {
     const int b = blockIdx.x;
     float* Ps = P + blockIdx.y * p_stride;
     const float* md = med + blockIdx.y * med_stride;
-    const int64_t start = 1 + (int64_t)b * W;
-    const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
-    auto two_c = [&](int bb) -> int64_t {
-        int64_t n_b = (bb == nblk - 1) ? (M - (int64_t)bb * W) : W;
-        return 2 * (int64_t)bb * W + n_b + 1;
+    const int Mi = (int)M;
+    const int start = 1 + b * W;
+    const int cnt = (Mi - b * W) < W ? (Mi - b * W) : W;
+    auto two_c = [&](int bb) -> int {
+        const int n_b = (bb == nblk - 1) ? (Mi - bb * W) : W;
+        return 2 * bb * W + n_b + 1;
     };
-    const int64_t c_here = two_c(b);
+    const int c_here = two_c(b);
     const float m_here = md[b];
-    // left neighbour segment [c_{b-1}, c_b), right [c_b, c_{b+1})
+    // left segment [c_{b-1}, c_b), right [c_b, c_{b+1}); flat outside the first/last centre
     const bool has_l = b > 0, has_r = b + 1 < nblk;
-    const int64_t c_l = has_l ? two_c(b - 1) : c_here, c_r = has_r ? two_c(b + 1) : c_here;
+    const int c_l = has_l ? two_c(b - 1) : c_here, c_r = has_r ? two_c(b + 1) : c_here;
     const float m_l = has_l ? md[b - 1] : m_here, m_r = has_r ? md[b + 1] : m_here;
-    const float inv_l = has_l ? 1.0f / (float)(c_here - c_l) : 0.0f;
-    const float inv_r = has_r ? 1.0f / (float)(c_r - c_here) : 0.0f;
+    const float s_l = has_l ? (m_here - m_l) / (float)(c_here - c_l) : 0.0f;
+    const float s_r = has_r ? (m_r - m_here) / (float)(c_r - c_here) : 0.0f;
+    const float base_l = has_l ? (float)c_l : (float)c_here;
+    const float ml0 = has_l ? m_l : m_here;
+    const float fc = (float)c_here;
+    constexpr float LN2 = 0.69314718055994530942f;
+#pragma unroll 4
     for (int i = threadIdx.x; i < cnt; i += NT) {
-        int64_t q = start + i;
-        int64_t tq = 2 * q;
-        float level;
-        if (tq < c_here) {
-            level = has_l ? m_l + (m_here - m_l) * ((float)(tq - c_l) * inv_l) : m_here;
-        } else {
-            level = has_r ? m_here + (m_r - m_here) * ((float)(tq - c_here) * inv_r) : m_here;
-        }
-        float p = Ps[q];
-        Ps[q] = level > 0.0f ? (p * 0.69314718055994530942f) / level : 0.0f;
+        const int q = start + i;
+        const float x = (float)(2 * q);
+        const bool left = x < fc;
+        const float level = left ? fmaf(s_l, x - base_l, ml0) : fmaf(s_r, x - fc, m_here);
+        const float p = Ps[q];
+        Ps[q] = level > 0.0f ? p * (LN2 * __builtin_amdgcn_rcpf(level)) : 0.0f;
     }
     if (b == 0 && threadIdx.x == 0) Ps[0] = 0.0f;
 }
@@ -898,6 +913,56 @@ __device__ __forceinline__ void fold_tile(const float* seg, const int* s_base, i
     }
 }
 
+// Common case: a full tile inside every fold's search range and no
+// inspection output.  The folds accumulate as above and are all kept; one
+// comparison per fold (the largest of a thread's bins against the threshold)
+// and one ballot decide whether the wave has any bin above a threshold, and
+// only then are the per-bin tests and appends run.
+template <int NF>
+__device__ __forceinline__ void fold_tile_fast(const float* seg, const int* s_base, int k0, const PeakParams& pp,
+                                               uint4* __restrict__ ring, uint32_t* __restrict__ counter,
+                                               uint32_t tid)
+{
+    constexpr int R4 = HT / NT;
+    const int kt = k0 + (int)threadIdx.x;
+    float acc[NF][R4];
+    {
+        const int b = s_base[16] + kt;
+#pragma unroll
+        for (int r = 0; r < R4; ++r) acc[0][r] = seg[b + NT * r];
+    }
+#pragma unroll
+    for (int l = 1; l < NF; ++l) {
+#pragma unroll
+        for (int r = 0; r < R4; ++r) acc[l][r] = acc[l - 1][r];
+#pragma unroll
+        for (int m = 1; m < (1 << l); m += 2) {
+            const int j = m << (4 - l);
+            const int b = s_base[j] + ((j * kt + 8) >> 4);
+#pragma unroll
+            for (int r = 0; r < R4; ++r) acc[l][r] += seg[b + 16 * j * r];
+        }
+    }
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) {
+        float mx = acc[l][0];
+#pragma unroll
+        for (int r = 1; r < R4; ++r) mx = fmaxf(mx, acc[l][r]);
+        any = any || mx > pp.thr[l];
+    }
+    if (__ballot(any)) {
+        const int lane = threadIdx.x & 63;
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int l = 0; l < NF; ++l)
+#pragma unroll
+            for (int r = 0; r < R4; ++r)
+                emit(acc[l][r] > pp.thr[l], lane, below, counter, ring, pp.capacity, tid, kt + NT * r,
+                     (pp.series_id << 8) | (uint32_t)l, acc[l][r]);
+    }
+}
+
 template <int NF>
 __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, size_t p_stride, int64_t M,
                                                 int tmpl_base, PeakParams pp, uint4* __restrict__ ring,
@@ -918,13 +983,26 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
 
     const float* seg = reinterpret_cast<const float*>(seg4);
     const uint32_t tid = pp.first_template_id + (uint32_t)(tmpl_base + (int)blockIdx.y);
-    if (kend == k0 + HT - 1)
+    const bool full = kend == k0 + HT - 1;
+    bool inside = full && !sums_out;
+#pragma unroll
+    for (int l = 0; l < NF; ++l) inside = inside && k0 >= pp.klo[l] && kend <= pp.khi[l];
+    if (inside)
+        fold_tile_fast<NF>(seg, s_base, k0, pp, ring, counter, tid);
+    else if (full)
         fold_tile<NF, true>(seg, s_base, k0, kend, M, pp, ring, counter, sums_out, tid);
     else
         fold_tile<NF, false>(seg, s_base, k0, kend, M, pp, ring, counter, sums_out, tid);
 }
 
 // ------------------------------------------------------------------------
+int ilog2i(int v)
+{
+    int r = 0;
+    while ((1 << (r + 1)) <= v) ++r;
+    return r;
+}
+
 template <int S, int C1>
 hipError_t fft1_launch(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int nslots,
                        const Slots& ws, int32_t* src_out, hipStream_t s)
@@ -939,7 +1017,8 @@ template <int R, int D2>
 hipError_t fft2_launch(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
 {
     dim3 grid(g.S / D2, nslots);
-    hipLaunchKernelGGL((k_fft2<R, D2>), grid, dim3(D2 * R / 16), 0, s, ws.Y, ws.y_stride, g.S, g.C1, ws.P,
+    hipLaunchKernelGGL((k_fft2<R, D2>), grid, dim3(D2 * R / 16), 0, s, ws.Y, ws.y_stride, g.S, ilog2i(g.S),
+                       ilog2i(g.C1), ws.P,
                        ws.p_stride, g.M, g.twst, g.tw2M_lo, g.tw2M_hi);
     return hipGetLastError();
 }

@@ -90,3 +90,19 @@ def test_served_results_equal_alone(tb, tight_budget):
         assert rep.budget_waits > 0 and rep.max_in_flight <= 2
     for r, a in zip(rq, ref):
         assert np.array_equal(r.candidates, a)
+
+
+def test_one_request_spread_over_idle_lanes(tb):
+    """A request of many waves on a plan whose other lanes are idle runs its
+    waves on all of them; the candidates are those of a single-lane plan."""
+    lens, series = _pool()
+    rng = np.random.default_rng(504)
+    tm = synth.uniform_templates(rng, 61, (0.3, 2.0), (0.0, 0.5), ecc_max=0.05)
+    out = []
+    for lanes in (1, 3):
+        with tb.Plan(fmin_hz=2.0, ring_capacity=1 << 16, lanes=lanes, batch_templates=8) as plan:
+            sid = plan.load_series(series[1], 64e-6)
+            out.append(plan.search(sid, tm, first_template_id=7))
+            out.append(plan.search(sid, tm[:5], first_template_id=500))
+    assert np.array_equal(out[0], out[2])
+    assert np.array_equal(out[1], out[3])
