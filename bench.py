@@ -52,7 +52,7 @@ def workload(name: str, templates: int | None):
     raise SystemExit("unknown workload " + name)
 
 
-DEFAULT_TILE = 16384  # FFT points per workgroup when the plan chooses
+DEFAULT_TILE = 8192  # FFT points per workgroup when the plan chooses
 
 
 def describe(w, name):

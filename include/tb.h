@@ -65,8 +65,8 @@ typedef struct {
     uint32_t lanes;            /* streams requests are spread over (1..16); work on different
                                   lanes overlaps on the device.  Lane 0 is `stream`. */
     uint32_t flags;            /* reserved, 0 */
-    uint32_t tile_points;      /* FFT points per workgroup: 16384, or 8192 (two workgroups per
-                                  compute unit); 0 = the plan's choice (16384) */
+    uint32_t tile_points;      /* FFT points per workgroup: 8192 (two workgroups per compute
+                                  unit) or 16384 (one); 0 = the plan's choice (8192) */
 } tb_config;
 
 /* One Keplerian orbital template (Sec. 2.1): P_orb = 2 pi / Omega, tau = a sin(eps)/c,

@@ -250,7 +250,7 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     g.log2n = log2n;
     g.n = (int64_t)1 << log2n;
     g.M = g.n / 2;
-    g.TE = p->cfg.tile_points ? (int)p->cfg.tile_points : 16384;
+    g.TE = p->cfg.tile_points ? (int)p->cfg.tile_points : 8192;
     const int64_t TE = std::min<int64_t>(g.TE, g.M);
     g.R = (int)std::max<int64_t>(16, g.M / g.TE);
     g.S = (int)(g.M / g.R);

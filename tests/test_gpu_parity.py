@@ -73,7 +73,7 @@ def test_stages_match_oracle(tb, lg, ts, W, tm):
 
 
 TILE_CASES = [
-    # 8192-point tiles: pass-1 columns C1 = 2 and 1, pass-2 transforms of 16 .. 256 points
+    # 16384-point tiles (one workgroup per CU): pass-1 columns C1 = 16 .. 1, pass-2 transforms of 16 and 64 points
     (15, 256e-6, 3000, (900.0, 0.8, 1.0, 0.3, 2.5)),
     (17, 64e-6, 4096, (7200.0, 0.5, 1.0, 0.0, 0.0)),
     (19, 64e-6, 2048, (3000.0, 2.0, 0.1, 0.0, 0.0)),
@@ -82,11 +82,11 @@ TILE_CASES = [
 
 
 @pytest.mark.parametrize("lg,ts,W,tm", TILE_CASES)
-def test_stages_match_oracle_8192_point_tiles(tb, lg, ts, W, tm):
+def test_stages_match_oracle_16384_point_tiles(tb, lg, ts, W, tm):
     n = 1 << lg
-    _say("stages (8192-point tiles) n=2^%d W=%d tm=%s" % (lg, W, tm))
+    _say("stages (16384-point tiles) n=2^%d W=%d tm=%s" % (lg, W, tm))
     x = _series(n, ts, seed=100 + lg, red=True, orbit=synth.Orbit(*tm), pspin=0.017)
-    with tb.Plan(whiten_window=W, tile_points=8192) as plan:
+    with tb.Plan(whiten_window=W, tile_points=16384) as plan:
         sid = plan.load_series(x, ts)
         ex = _stage_check(tb, plan, sid, x, n, ts, tm, W)
         _say("  tie-exempt indices:", ex)
