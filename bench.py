@@ -28,9 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNELS = ["k_fft1 (delay + resample + FFT pass 1)", "k_fft2 (FFT pass 2 + R2C + power)",
-           "k_median (whitening medians)", "k_whiten (whitening)", "k_harmsum (harmonic sum + peaks)"]
-KERNEL_SHORT = ["k_fft1", "k_fft2", "k_median", "k_whiten", "k_harmsum"]
+KERNELS = ["k_chunk_polys (per-template delay polynomials)", "k_fft1 (resample + FFT pass 1)",
+           "k_fft2 (FFT pass 2 + R2C + power)", "k_median (whitening medians)", "k_whiten (whitening)",
+           "k_harmsum (harmonic sum + peaks)"]
+KERNEL_SHORT = ["k_chunk_polys", "k_fft1", "k_fft2", "k_median", "k_whiten", "k_harmsum"]
+PROFILE_EVERY = 16  # time one wave in this many inside the timed region
 METRIC = "templates/s (resample+FFT+harmsum+peaks) at N=2^23 FP32"
 
 
@@ -68,14 +70,16 @@ def describe(w, name):
             "whiten_window": 4096}
 
 
-def kernel_bytes(n: int, templates_per_launch: float):
+def kernel_bytes(n: int, templates_per_launch: float, tile: int = 8192):
     """Algorithmic HBM bytes per launch of each kernel class, for series length n:
-    pass 1 writes the 4n-byte exchange per template and reads the 4n-byte series
-    once per launch; pass 2 reads 4n and writes 2n; the medians read the
-    2n-byte spectrum, the whitening reads and rewrites it, the harmonic sum
-    reads it once (first touch)."""
+    the delay polynomials write 48 B per 16 tile points; pass 1 writes the
+    4n-byte exchange per template and reads the 4n-byte series once per launch;
+    pass 2 reads 4n and writes 2n; the medians read the 2n-byte spectrum, the
+    whitening reads and rewrites it, the harmonic sum reads it once (first
+    touch)."""
     b = templates_per_launch
-    return [4.0 * n * b + 4.0 * n, 6.0 * n * b, 2.0 * n * b, 4.0 * n * b, 2.0 * n * b]
+    return [48.0 * min(tile, n // 2) / 16 * b, 4.0 * n * b + 4.0 * n, 6.0 * n * b, 2.0 * n * b, 4.0 * n * b,
+            2.0 * n * b]
 
 
 def traffic_record(kernel: str, workload_name: str):
@@ -117,18 +121,18 @@ def cpu_baseline(w, seconds_hint: float):
             "single_thread_templates_per_s": 1.0 / one}
 
 
-def kernel_report(plan, n_avg: float, workload_name: str):
+def kernel_report(plan, n_avg: float, workload_name: str, tile: int):
     ms, launches, tmpl = plan.profile_read()
     plan.profile(False)
     per = []
-    for k in range(5):
+    for k in range(len(KERNELS)):
         L = max(1, int(launches[k]))
         avg_ms = ms[k] / L
-        byt = kernel_bytes(int(n_avg), tmpl / L)[k]
+        byt = kernel_bytes(int(n_avg), tmpl / L, tile)[k]
         per.append({"kernel": KERNEL_SHORT[k], "desc": KERNELS[k], "launches": int(launches[k]), "avg_ms": avg_ms,
                     "total_ms": float(ms[k]), "bytes_per_launch": byt,
                     "gbs": byt / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None})
-    dom = max(range(5), key=lambda k: ms[k])
+    dom = max(range(len(KERNELS)), key=lambda k: ms[k])
     d = per[dom]
     tr = traffic_record(d["kernel"], workload_name)
     roof = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -178,7 +182,7 @@ def run_bank(args, tb, torch):
     conf = describe(w, args.workload)
     conf["tile_points"] = args.tile or DEFAULT_TILE
     conf["requests_per_series"] = max(1, args.split)
-    lanes = args.lanes or (4 if len(w.series) > 1 else max(1, args.split))
+    lanes = args.lanes or 4
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
                    threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18,
                    tile_points=args.tile)
@@ -202,7 +206,7 @@ def run_bank(args, tb, torch):
         step()
     torch.cuda.synchronize()
     if not args.no_profile:
-        plan.profile(True)
+        plan.profile(PROFILE_EVERY)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ncand = 0
@@ -222,7 +226,8 @@ def run_bank(args, tb, torch):
            "algorithmic_gbs": 12.0 * samples_total * ntemp * args.steps / dt / 1e9}
     out["algorithmic_hbm_frac"] = out["algorithmic_gbs"] / PEAK_HBM_GBS
     if not args.no_profile:
-        out["kernels"], out["roofline"] = kernel_report(plan, samples_total / len(w.series), args.workload)
+        out["kernels"], out["roofline"] = kernel_report(plan, samples_total / len(w.series), args.workload,
+                                                     conf["tile_points"])
         out["stream_copy_gbs"] = stream_copy_gbs(plan, tb)
     plan.close()
     if args.workload == "c4" and not args.no_plain:

@@ -170,18 +170,20 @@ tb_status tb_thresholds(tb_plan_t plan, float out[5]);
  * measured with HIP events on the plan stream (0 if none). */
 tb_status tb_last_request_ms(tb_plan_t plan, int64_t request_id, double* ms);
 
-/* Per-kernel device timing: with profiling on, HIP events are recorded on the
- * plan stream before, between and after the kernels of every wave.
- * enable != 0 clears earlier measurements and starts a new one; 0 stops. */
-tb_status tb_profile(tb_plan_t plan, int enable);
+/* Per-kernel device timing: with profiling on, HIP events are recorded on a
+ * wave's stream before, between and after its kernels, for every `every`-th
+ * wave queued (1 = all; a sample keeps the events' own cost out of the
+ * measured throughput).  every > 0 clears earlier measurements and starts a
+ * new one; 0 stops.  Negative values are rejected. */
+tb_status tb_profile(tb_plan_t plan, int every);
 
 /* Waits for queued work and reports, per kernel class, the summed device
- * milliseconds and launch counts since tb_profile(plan, 1):
- *   [0] resample + FFT pass 1, [1] FFT pass 2 + power, [2] block medians,
- *   [3] whitening, [4] harmonic sum + threshold + compaction.
- * *templates receives the number of templates those launches processed.
+ * milliseconds and launch counts of the timed waves since profiling started:
+ *   [0] delay polynomials, [1] resample + FFT pass 1, [2] FFT pass 2 + power,
+ *   [3] block medians, [4] whitening, [5] harmonic sum + threshold + compaction.
+ * *templates receives the number of templates the timed waves processed.
  * Any output pointer may be NULL. */
-tb_status tb_profile_read(tb_plan_t plan, double ms[5], uint64_t launches[5], uint64_t* templates);
+tb_status tb_profile_read(tb_plan_t plan, double ms[6], uint64_t launches[6], uint64_t* templates);
 
 /* Streaming copy of bytes (a multiple of 16) between two device buffers on the
  * plan stream, repeated reps times; *ms receives the mean device time of one

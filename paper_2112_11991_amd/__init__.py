@@ -251,14 +251,16 @@ def tb_last_request_ms(plan: int, request_id: int) -> float:
     return ms.value
 
 
-def tb_profile(plan: int, enable: bool) -> None:
-    _check(_L.tb_profile(C.c_void_p(plan), int(bool(enable))), "tb_profile")
+def tb_profile(plan: int, every: int) -> None:
+    """Time every `every`-th wave (True = 1, False/0 = off)."""
+    _check(_L.tb_profile(C.c_void_p(plan), int(every)), "tb_profile")
 
 
 def tb_profile_read(plan: int):
-    """(ms[5], launches[5], templates): pass 1, pass 2, medians, whitening, harmonic sum."""
-    ms = np.zeros(5, dtype=np.float64)
-    ln = np.zeros(5, dtype=np.uint64)
+    """(ms[6], launches[6], templates): delay polynomials, pass 1, pass 2, medians,
+    whitening, harmonic sum."""
+    ms = np.zeros(6, dtype=np.float64)
+    ln = np.zeros(6, dtype=np.uint64)
     t = C.c_uint64(0)
     _check(_L.tb_profile_read(C.c_void_p(plan), _ptr(ms), _ptr(ln), C.byref(t)), "tb_profile_read")
     return ms, ln, int(t.value)
@@ -381,8 +383,9 @@ class Plan:
     def set_budget(self, budget_bytes):
         tb_set_budget(self.handle, budget_bytes)
 
-    def profile(self, enable=True):
-        tb_profile(self.handle, enable)
+    def profile(self, every=1):
+        """Time every `every`-th wave (0 stops)."""
+        tb_profile(self.handle, int(every))
 
     def profile_read(self):
         return tb_profile_read(self.handle)

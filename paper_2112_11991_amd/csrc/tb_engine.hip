@@ -175,8 +175,9 @@ struct tb_plan_s {
     uint64_t held = 0;
     double thr[5] = {0, 0, 0, 0, 0};
     double* d_partial = nullptr;
-    bool profiling = false;
-    std::vector<std::vector<hipEvent_t>> prof_events;  // K_CLASSES + 1 per wave
+    uint32_t prof_every = 0;                           // time every k-th wave; 0 = off
+    uint64_t prof_wave = 0;                            // waves queued since profiling started
+    std::vector<std::vector<hipEvent_t>> prof_events;  // K_CLASSES + 1 per timed wave
     uint64_t prof_templates = 0;
 };
 
@@ -402,7 +403,7 @@ tb_status enqueue(tb_plan_t p, const Crew& crew, const SeriesRec& sr, Geometry* 
         hipStream_t stream = crew.streams[wave % nc];
         int nslots = (int)std::min<uint32_t>((uint32_t)ws->B, count - w0);
         hipEvent_t* ev = nullptr;
-        if (p->profiling) {
+        if (p->prof_every && p->prof_wave++ % p->prof_every == 0) {
             std::vector<hipEvent_t> evs(K_CLASSES + 1, nullptr);
             for (auto& e : evs)
                 if (hipEventCreate(&e) != hipSuccess) return TB_ERR_DEVICE;
@@ -908,29 +909,30 @@ tb_status tb_last_request_ms(tb_plan_t p, int64_t rid, double* ms)
     return TB_OK;
 }
 
-tb_status tb_profile(tb_plan_t p, int enable)
+tb_status tb_profile(tb_plan_t p, int every)
 {
-    if (!p) return TB_ERR_INVALID_ARG;
+    if (!p || every < 0) return TB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(p->mu);
-    if (enable) {
+    if (every) {
         TB_TRY(hipSetDevice(p->cfg.device));
         TB_TRY(sync_lanes(p));
         for (auto& v : p->prof_events)
             for (auto e : v) hipEventDestroy(e);
         p->prof_events.clear();
         p->prof_templates = 0;
+        p->prof_wave = 0;
     }
-    p->profiling = enable != 0;
+    p->prof_every = (uint32_t)every;
     return TB_OK;
 }
 
-tb_status tb_profile_read(tb_plan_t p, double ms[5], uint64_t launches[5], uint64_t* templates)
+tb_status tb_profile_read(tb_plan_t p, double ms[6], uint64_t launches[6], uint64_t* templates)
 {
     if (!p) return TB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(p->mu);
     TB_TRY(hipSetDevice(p->cfg.device));
     TB_TRY(sync_lanes(p));
-    double acc[K_CLASSES] = {0, 0, 0, 0, 0};
+    double acc[K_CLASSES] = {0, 0, 0, 0, 0, 0};
     for (auto& v : p->prof_events)
         for (int k = 0; k < K_CLASSES; ++k) {
             float f = 0.0f;

@@ -83,11 +83,12 @@ struct Inspect {
 
 hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, hipStream_t s);
 hipError_t launch_mean_subtract(const float* in, float* out, int64_t n, double* partial, hipStream_t s);
-// Kernel classes timed by the plan's profiler.
-enum { K_PASS1 = 0, K_PASS2 = 1, K_MEDIAN = 2, K_WHITEN = 3, K_HARMSUM = 4, K_CLASSES = 5 };
+// Kernel classes timed by the plan's profiler, in launch order.
+enum { K_POLY = 0, K_PASS1 = 1, K_PASS2 = 2, K_MEDIAN = 3, K_WHITEN = 4, K_HARMSUM = 5, K_CLASSES = 6 };
 
-// Queues the four kernels of one wave of nslots templates.  ev, if not null,
-// holds K_CLASSES + 1 events recorded before, between and after them.
+// Queues the kernels of one wave of nslots templates.  ev, if not null, holds
+// K_CLASSES + 1 events recorded before, between and after them (event k
+// before class k, event K_CLASSES after the last).
 hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
                        int nslots, const Slots& ws, const PeakParams& pp, uint4* ring, uint32_t* counter,
                        const Inspect& ins, hipStream_t s, hipEvent_t* ev = nullptr);

@@ -577,6 +577,12 @@ __device__ __forceinline__ float power_of(float2 z, float2 zm, float2 w)
 // Z at k = k2 + S k1, and Z_{M-k} sits in the mirror slot at k1' = R-1-k1
 // (in column 0 at (R - k1) mod R).  Each slot emits |X|^2 for its own bins:
 // runs of D consecutive bins per k1, ascending for A, descending for mirrors.
+//
+// With R > 16 every pass-1 workgroup held one column (C1 = 1); thread t then
+// loads slot q = t % D2 of blocks w = t / D2 + RK i and emits bins
+// k1 = t / D2 + RK i of that slot, so all of its addresses are a per-thread
+// base plus compile-time steps.  R = 16 (short series) takes the general
+// index arithmetic.
 template <int R, int D2>
 __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__ Y, size_t y_stride, int S, int lgS,
                                                       int lgC1, float* __restrict__ P, size_t p_stride, int64_t M,
@@ -585,59 +591,85 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
                                                       const float2* __restrict__ tw2M_hi)
 {
     constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2, RK = R / 16, LD2 = Log2<D2>::value;
+    constexpr bool ONE_COLUMN = R > 16;
     __shared__ float2 lds[D2 * LSP];
     const int g = xcd_remap(blockIdx.x, S / D2);
     const float2* Ys = Y + blockIdx.y * y_stride;
     float* Ps = P + blockIdx.y * p_stride;
-    const int cmask = (1 << lgC1) - 1;
+    const int q = (int)threadIdx.x & (D2 - 1), k1t = (int)threadIdx.x >> LD2;
+    const int a = g * D + (q < D ? q : q - D);
+    const int col = q < D ? a : (a == 0 ? S / 2 : S - a);
 
-    // element e = (w, q, c): block w of pass 1, slot q, column c (C1 = 2^lgC1)
-    float2 v[16];
-    int laddr[16];
+    if constexpr (ONE_COLUMN) {
+        // element i: block w = k1t + RK i, column col
+        const uint32_t off0 = ((((uint32_t)k1t << lgS) + (uint32_t)col) << 3);
+        const uint32_t step = (uint32_t)RK << (lgS + 3);
+        float2 v[16];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int e = (int)threadIdx.x + i * T;
-        const int c = e & cmask, q = (e >> lgC1) & (D2 - 1), w = e >> (lgC1 + LD2);
-        const int a = g * D + (q < D ? q : q - D);
-        const int col = q < D ? a : (a == 0 ? S / 2 : S - a);
-        const uint32_t src = ((((uint32_t)w << lgS) + (uint32_t)col) << lgC1) | (uint32_t)c;
-        v[i] = Ys[src];
-        laddr[i] = q * LSP + pidx((w << lgC1) | c);
+        for (int i = 0; i < 16; ++i)
+            v[i] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(Ys) + (off0 + step * (uint32_t)i));
+        float2* dst = lds + q * LSP + pidx(k1t);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) dst[pidx(RK * i)] = v[i];
+    } else {
+        // element e = (w, q, c): block w of pass 1, slot q, column c (C1 = 2^lgC1)
+        const int cmask = (1 << lgC1) - 1;
+        float2 v[16];
+        int laddr[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = (int)threadIdx.x + i * T;
+            const int c = e & cmask, qe = (e >> lgC1) & (D2 - 1), w = e >> (lgC1 + LD2);
+            const int ae = g * D + (qe < D ? qe : qe - D);
+            const int cole = qe < D ? ae : (ae == 0 ? S / 2 : S - ae);
+            const uint32_t src = ((((uint32_t)w << lgS) + (uint32_t)cole) << lgC1) | (uint32_t)c;
+            v[i] = Ys[src];
+            laddr[i] = qe * LSP + pidx((w << lgC1) | c);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lds[laddr[i]] = v[i];
     }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) lds[laddr[i]] = v[i];
     __syncthreads();
     fft_tile<R, D2>(lds, twst);
 
-    // Thread t emits slot q = t % D2 at k1 = t / D2 + RK i.  The split twiddle
+    // Thread t emits slot q at k1 = k1t + RK i.  The split twiddle
     // W_2M^{col + S k1} advances by W_2M^{S RK} = W_32 per step.
-    const int q = (int)threadIdx.x % D2, k1t = (int)threadIdx.x / D2;
-    const int a = g * D + (q < D ? q : q - D);
-    int col, pq;
-    if (q < D) {
-        col = a;
-        pq = (a == 0) ? q : q + D;
-    } else {
-        col = (a == 0) ? S / 2 : S - a;
-        pq = (a == 0) ? q : q - D;
-    }
+    const int pq = (a == 0) ? q : (q < D ? q + D : q - D);
     const bool self = q < D && a == 0;  // column 0: Z_{M-k} at k1' = (R - k1) mod R
     float2 w = twiddle2(tw2M_lo, tw2M_hi, (uint32_t)col + (uint32_t)S * (uint32_t)k1t);
     const float2 z = make_float2(0.98078528040323044913f, -0.19509032201612826785f);
-    const float2* own = lds + q * LSP;
-    const float2* mir = lds + pq * LSP;
+    const uint32_t soff0 = ((uint32_t)col + ((uint32_t)k1t << lgS)) << 2;
+    const uint32_t sstep = (uint32_t)RK << (lgS + 2);
+    auto store = [&](int i, float v) {
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(Ps) + (soff0 + sstep * (uint32_t)i)) = v;
+    };
+    if (self && k1t == 0) {
+        // bins k1 = RK i of column 0; bin 0 pairs with itself, and the
+        // Nyquist bin M comes from Z_0 as well
+        const float2* own = lds + q * LSP;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int k1 = k1t + RK * i;
-        const int pk = self ? ((R - k1) & (R - 1)) : R - 1 - k1;
-        const float2 zo = own[pidx(k1)];
-        const float2 zm = mir[pidx(pk)];
-        const uint32_t k = (uint32_t)col + (uint32_t)S * (uint32_t)k1;
-        Ps[k] = power_of(zo, zm, w);
-        w = cmul(w, z);
-        if (i == 0 && self && k1 == 0) {
-            const float sm = zo.x - zo.y;
-            Ps[M] = sm * sm;
+        for (int i = 0; i < 16; ++i) {
+            const int k1 = RK * i;
+            const float2 zo = own[pidx(k1)];
+            const float2 zm = own[pidx((R - k1) & (R - 1))];
+            store(i, power_of(zo, zm, w));
+            w = cmul(w, z);
+            if (i == 0) {
+                const float sm = zo.x - zo.y;
+                Ps[M] = sm * sm;
+            }
+        }
+    } else {
+        // mirror index R-1-k1 (R-k1 in column 0) = RK (15 - i) + m0 with m0 < RK
+        const int m0 = self ? RK - k1t : RK - 1 - k1t;
+        const float2* own = lds + q * LSP + pidx(k1t);
+        const float2* mir = lds + pq * LSP + pidx(m0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const float2 zo = own[pidx(RK * i)];
+            const float2 zm = mir[pidx(RK * (15 - i))];
+            store(i, power_of(zo, zm, w));
+            w = cmul(w, z);
         }
     }
 }
@@ -780,15 +812,15 @@ __global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_s
 // compaction, on the whitened spectrum.
 //
 // Bin k of fold h adds harmonic m at bin floor((2mk + h)/(2h)); with
-// j = 16 m / h that is floor((jk + 8)/16), so an output tile [k0, k0+HT)
-// needs, for each j, the contiguous input run
-// [floor((j k0 + 8)/16), floor((j (k0+HT-1) + 8)/16)], about 8.5 HT bins in
-// all.  Each run is staged once in LDS.  A thread handles bins k0 + t + NT i;
-// moving i by one moves the run-j index by exactly 16 j, so every LDS address
-// is a per-thread base plus a compile-time offset.  Fold 2h adds the odd m of
-// the new fold to fold h (ascending m), the order the oracle uses.
-constexpr int HT = 1024;                   // output bins per workgroup
-constexpr int HSEG4 = (17 * HT) / 8 + 48;  // LDS float4 slots for the 16 runs (16-byte aligned)
+// j = 16 m / h that is floor((jk + 8)/16).  A workgroup handles the HT bins
+// [k0, k0 + HT), thread t the bins k0 + t + NT r (r < HT/NT); moving r by one
+// moves every harmonic index by exactly 16 j, so each thread computes one
+// index per j and reads the rest at compile-time offsets.  Lanes of a wave
+// hold consecutive bins, so a wave's read of harmonic j covers about 4j
+// consecutive floats: the loads go straight to L2 (no LDS staging, no
+// barrier), which leaves occupancy to the register count.  Fold 2h adds the
+// odd m of the new fold to fold h (ascending m), the order the oracle uses.
+constexpr int HT = 1024;  // output bins per workgroup
 
 // One fold's threshold test and wave-ballot append of the bins above it.
 __device__ __forceinline__ void emit(bool hit, int lane, uint64_t below, uint32_t* __restrict__ counter,
@@ -808,129 +840,20 @@ __device__ __forceinline__ void emit(bool hit, int lane, uint64_t below, uint32_
     }
 }
 
-// Which of the four waves stages run j (runs are about j HT/16 bins long):
-// a balanced split for 16 harmonics, round robin otherwise.
-__host__ __device__ constexpr int run_owner(int j, int NF)
-{
-    return NF == 5 ? ((j == 16 || j == 15 || j == 3) ? 0 : (j == 14 || j == 13 || j == 5 || j == 2) ? 1
-                      : (j == 12 || j == 11 || j == 10 || j == 1) ? 2 : 3)
-         : NF == 4 ? ((j == 16 || j == 2) ? 0 : (j == 14 || j == 4) ? 1 : (j == 12 || j == 6) ? 2 : 3)
-                   : ((j / (16 >> (NF - 1))) & 3);
-}
-
-template <int NF, int J>
-struct StageRuns {
-    // float4 slot offset of run J within the tile's LDS segment
-    static __device__ __forceinline__ void run(const float4* __restrict__ P4, float4* seg4, int k0, int kend,
-                                               int off, int wave, int lane, int* s_base)
-    {
-        constexpr int JSTEP = 16 >> (NF - 1);
-        const int lo4 = ((J * k0 + 8) >> 4) >> 2, hi4 = ((J * kend + 8) >> 4) >> 2, n4 = hi4 - lo4 + 1;
-        if (wave == run_owner(J, NF)) {
-            constexpr int U = (J * HT / 64 + 8) / 64 + 1;  // slots per lane, n4 <= J HT / 64 + 2
-            float4 r[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = lane + 64 * u;
-                float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                if (i < n4) t = P4[lo4 + i];
-                r[u] = t;
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = lane + 64 * u;
-                if (i < n4) seg4[off + i] = r[u];
-            }
-            if (lane == 0) s_base[J] = 4 * (off - lo4);
-        }
-        StageRuns<NF, J + JSTEP>::run(P4, seg4, k0, kend, off + n4, wave, lane, s_base);
-    }
-};
-template <int NF>
-struct StageRuns<NF, 17> {
-    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
-};
-template <int NF>
-struct StageRuns<NF, 18> {
-    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
-};
-template <int NF>
-struct StageRuns<NF, 20> {
-    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
-};
-template <int NF>
-struct StageRuns<NF, 24> {
-    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
-};
-template <int NF>
-struct StageRuns<NF, 32> {
-    static __device__ __forceinline__ void run(const float4* __restrict__, float4*, int, int, int, int, int, int*) {}
-};
-
-// Folds of the HT/NT bins k = k0 + t + NT r of one thread.  Bin k of fold
-// 2h adds P^[floor((jk + 8)/16)] for the odd m of the fold, j = 16 m / (2h),
-// in ascending m; moving r by one moves the run-j index by exactly 16 j.
-// FULL tiles need no bounds test.
+// Fold sums of a thread's R4 bins.  FULL tiles end at or below M, so no
+// index can pass it; the last tile clamps its indices (bins beyond M are not
+// reported).
 template <int NF, bool FULL>
-__device__ __forceinline__ void fold_tile(const float* seg, const int* s_base, int k0, int kend, int64_t M,
-                                          const PeakParams& pp, uint4* __restrict__ ring,
-                                          uint32_t* __restrict__ counter, float* __restrict__ sums_out,
-                                          uint32_t tid)
+__device__ __forceinline__ void fold_sums(const float* __restrict__ Ps, int kt, int M, float (&acc)[NF][HT / NT])
 {
     constexpr int R4 = HT / NT;
-    const int lane = threadIdx.x & 63;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int kt = k0 + (int)threadIdx.x;
-    float acc[R4];
-    bool in[R4];
-    {
-        const int b = s_base[16] + kt;
+    auto at = [&](int j, int r) -> float {
+        if (FULL) return (Ps + ((j * kt + 8) >> 4))[16 * j * r];  // one address per j, immediate offsets
+        const int i = ((j * kt + 8) >> 4) + 16 * j * r;
+        return Ps[i < M ? i : M];
+    };
 #pragma unroll
-        for (int r = 0; r < R4; ++r) {
-            in[r] = FULL || kt + NT * r <= kend;
-            acc[r] = in[r] ? seg[b + NT * r] : 0.0f;
-        }
-    }
-#pragma unroll
-    for (int l = 0; l < NF; ++l) {
-        if (l > 0) {
-#pragma unroll
-            for (int m = 1; m < (1 << l); m += 2) {
-                const int j = m << (4 - l);
-                const int b = s_base[j] + ((j * kt + 8) >> 4);
-#pragma unroll
-                for (int r = 0; r < R4; ++r)
-                    if (FULL || in[r]) acc[r] += seg[b + 16 * j * r];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < R4; ++r) {
-            const int k = kt + NT * r;
-            if (sums_out && in[r]) sums_out[(size_t)l * (M + 1) + k] = acc[r];
-            const bool hit = in[r] && k >= pp.klo[l] && k <= pp.khi[l] && acc[r] > pp.thr[l];
-            emit(hit, lane, below, counter, ring, pp.capacity, tid, k, (pp.series_id << 8) | (uint32_t)l, acc[r]);
-        }
-    }
-}
-
-// Common case: a full tile inside every fold's search range and no
-// inspection output.  The folds accumulate as above and are all kept; one
-// comparison per fold (the largest of a thread's bins against the threshold)
-// and one ballot decide whether the wave has any bin above a threshold, and
-// only then are the per-bin tests and appends run.
-template <int NF>
-__device__ __forceinline__ void fold_tile_fast(const float* seg, const int* s_base, int k0, const PeakParams& pp,
-                                               uint4* __restrict__ ring, uint32_t* __restrict__ counter,
-                                               uint32_t tid)
-{
-    constexpr int R4 = HT / NT;
-    const int kt = k0 + (int)threadIdx.x;
-    float acc[NF][R4];
-    {
-        const int b = s_base[16] + kt;
-#pragma unroll
-        for (int r = 0; r < R4; ++r) acc[0][r] = seg[b + NT * r];
-    }
+    for (int r = 0; r < R4; ++r) acc[0][r] = at(16, r);
 #pragma unroll
     for (int l = 1; l < NF; ++l) {
 #pragma unroll
@@ -938,28 +861,9 @@ __device__ __forceinline__ void fold_tile_fast(const float* seg, const int* s_ba
 #pragma unroll
         for (int m = 1; m < (1 << l); m += 2) {
             const int j = m << (4 - l);
-            const int b = s_base[j] + ((j * kt + 8) >> 4);
 #pragma unroll
-            for (int r = 0; r < R4; ++r) acc[l][r] += seg[b + 16 * j * r];
+            for (int r = 0; r < R4; ++r) acc[l][r] += at(j, r);
         }
-    }
-    bool any = false;
-#pragma unroll
-    for (int l = 0; l < NF; ++l) {
-        float mx = acc[l][0];
-#pragma unroll
-        for (int r = 1; r < R4; ++r) mx = fmaxf(mx, acc[l][r]);
-        any = any || mx > pp.thr[l];
-    }
-    if (__ballot(any)) {
-        const int lane = threadIdx.x & 63;
-        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-        for (int l = 0; l < NF; ++l)
-#pragma unroll
-            for (int r = 0; r < R4; ++r)
-                emit(acc[l][r] > pp.thr[l], lane, below, counter, ring, pp.capacity, tid, kt + NT * r,
-                     (pp.series_id << 8) | (uint32_t)l, acc[l][r]);
     }
 }
 
@@ -968,31 +872,50 @@ __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, siz
                                                 int tmpl_base, PeakParams pp, uint4* __restrict__ ring,
                                                 uint32_t* __restrict__ counter, float* __restrict__ sums_out)
 {
-    constexpr int JSTEP = 16 >> (NF - 1);
-    __shared__ float4 seg4[HSEG4];
-    __shared__ int s_base[17];
+    constexpr int R4 = HT / NT;
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     const int k0 = tile * HT;
-    const int kend = (int)(((int64_t)k0 + HT - 1) < M ? (int64_t)k0 + HT - 1 : M);
-    const float4* P4 = reinterpret_cast<const float4*>(P + blockIdx.y * p_stride);
-
-    // Run j holds P^ from bin 4 floor(lo_j / 4) on, lo_j = floor((j k0 + 8)/16);
-    // runs are packed in ascending j; each wave stages the runs it owns.
-    StageRuns<NF, JSTEP>::run(P4, seg4, k0, kend, 0, (int)threadIdx.x >> 6, (int)threadIdx.x & 63, s_base);
-    __syncthreads();
-
-    const float* seg = reinterpret_cast<const float*>(seg4);
+    const int Mi = (int)M;
+    const int kend = k0 + HT - 1 < Mi ? k0 + HT - 1 : Mi;
+    const float* Ps = P + blockIdx.y * p_stride;
     const uint32_t tid = pp.first_template_id + (uint32_t)(tmpl_base + (int)blockIdx.y);
+    const int kt = k0 + (int)threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const bool full = kend == k0 + HT - 1;
     bool inside = full && !sums_out;
 #pragma unroll
     for (int l = 0; l < NF; ++l) inside = inside && k0 >= pp.klo[l] && kend <= pp.khi[l];
-    if (inside)
-        fold_tile_fast<NF>(seg, s_base, k0, pp, ring, counter, tid);
-    else if (full)
-        fold_tile<NF, true>(seg, s_base, k0, kend, M, pp, ring, counter, sums_out, tid);
+
+    float acc[NF][R4];
+    if (full)
+        fold_sums<NF, true>(Ps, kt, Mi, acc);
     else
-        fold_tile<NF, false>(seg, s_base, k0, kend, M, pp, ring, counter, sums_out, tid);
+        fold_sums<NF, false>(Ps, kt, Mi, acc);
+
+    if (inside) {
+        // one comparison per fold (the largest of a thread's bins) and one
+        // ballot decide whether the wave has anything to report
+        bool any = false;
+#pragma unroll
+        for (int l = 0; l < NF; ++l) {
+            float mx = acc[l][0];
+#pragma unroll
+            for (int r = 1; r < R4; ++r) mx = fmaxf(mx, acc[l][r]);
+            any = any || mx > pp.thr[l];
+        }
+        if (!__ballot(any)) return;
+    }
+#pragma unroll
+    for (int l = 0; l < NF; ++l)
+#pragma unroll
+        for (int r = 0; r < R4; ++r) {
+            const int k = kt + NT * r;
+            const bool in = k <= kend;
+            if (sums_out && in) sums_out[(size_t)l * (M + 1) + k] = acc[l][r];
+            const bool hit = in && k >= pp.klo[l] && k <= pp.khi[l] && acc[l][r] > pp.thr[l];
+            emit(hit, lane, below, counter, ring, pp.capacity, tid, k, (pp.series_id << 8) | (uint32_t)l, acc[l][r]);
+        }
 }
 
 // ------------------------------------------------------------------------
@@ -1117,19 +1040,20 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
 {
     hipError_t e;
     const TmplDev* tmw = tm + tmpl_base;
-    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[K_POLY], s)) != hipSuccess) return e;
     const int nchunk = (int)(std::min<int64_t>(g.TE, g.M) / 16);
     hipLaunchKernelGGL(k_chunk_polys, dim3((nchunk + NT - 1) / NT, nslots), dim3(NT), 0, s, tmw, tsamp, g.R, g.C1,
                        nchunk, ws.poly, ws.poly_stride, ws.pok);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[K_PASS1], s)) != hipSuccess) return e;
     if ((e = launch_fft1(g, x, tsamp, tmw, nslots, ws, ins.src, s)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[K_PASS2], s)) != hipSuccess) return e;
     if ((e = launch_fft2(g, nslots, ws, s)) != hipSuccess) return e;
     if (ins.power &&
         (e = hipMemcpyAsync(ins.power, ws.P, sizeof(float) * (size_t)(g.M + 1), hipMemcpyDeviceToDevice, s)) !=
             hipSuccess)
         return e;
-    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[K_MEDIAN], s)) != hipSuccess) return e;
     if (g.W <= 16 * NT)
         hipLaunchKernelGGL((k_median<16>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
                            ws.med, ws.med_stride);
@@ -1137,11 +1061,11 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
         hipLaunchKernelGGL((k_median<32>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
                            ws.med, ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[K_WHITEN], s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk, ws.med,
                        ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[4], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[K_HARMSUM], s)) != hipSuccess) return e;
     int ntile = (int)((g.M + 1 + HT - 1) / HT);
     dim3 hg(ntile, nslots);
     switch (pp.nfold) {
@@ -1153,7 +1077,7 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
     default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[5], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[K_CLASSES], s)) != hipSuccess) return e;
     return hipSuccess;
 }
 

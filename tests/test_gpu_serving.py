@@ -106,3 +106,18 @@ def test_one_request_spread_over_idle_lanes(tb):
             out.append(plan.search(sid, tm[:5], first_template_id=500))
     assert np.array_equal(out[0], out[2])
     assert np.array_equal(out[1], out[3])
+
+
+def test_profile_samples_every_kth_wave(tb):
+    lens, series = _pool()
+    rng = np.random.default_rng(505)
+    tm = synth.uniform_templates(rng, 80, (0.3, 2.0), (0.0, 0.5))
+    with tb.Plan(fmin_hz=2.0, batch_templates=8) as plan:
+        sid = plan.load_series(series[0], 64e-6)
+        plan.profile(3)
+        plan.search(sid, tm)  # 10 waves of 8: waves 0, 3, 6, 9 are timed
+        ms, launches, ntemp = plan.profile_read()
+        plan.profile(0)
+    assert list(launches) == [4] * 6
+    assert ntemp == 32
+    assert (ms > 0).all()
