@@ -310,7 +310,7 @@ tb_status get_slots(tb_plan_t p, int lane, const Geometry& g, Slots** out)
     s.y_stride = (size_t)g.M;
     s.p_stride = ((size_t)g.M + 1 + 63) & ~(size_t)63;
     s.med_stride = ((size_t)g.nblk + 63) & ~(size_t)63;
-    s.poly_stride = (size_t)std::min<int64_t>(g.TE, g.M) / 16;
+    s.poly_stride = (size_t)std::min<int64_t>(g.TE, g.M) / 8;
     size_t by = sizeof(float2) * s.y_stride * s.B, bp = sizeof(float) * s.p_stride * s.B,
            bm = sizeof(float) * s.med_stride * s.B, bq = sizeof(ChunkPoly) * s.poly_stride * s.B,
            bk = sizeof(int32_t) * (size_t)s.B;

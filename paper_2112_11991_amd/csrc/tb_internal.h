@@ -42,7 +42,8 @@ constexpr int TWST_NS_MAX = 1024;           // largest stage stride (16384-point
 constexpr int SERIES_PAD = 64;              // zero samples after a resident series
 
 // Fourth-order expansion of the sample delay around sample jmid (one per
-// chunk of 16 pass-1 tile points), 48 bytes so that records stay 16-B aligned.
+// chunk of 16 or 8 pass-1 tile points), 48 bytes so that records stay 16-B
+// aligned.
 struct ChunkPoly {
     double c0, c1, c2, c3, c4;
     int32_t jmid, pad;
@@ -69,9 +70,9 @@ struct Slots {
     size_t p_stride = 0;
     float* med = nullptr;  // block medians, B x nblk
     size_t med_stride = 0;
-    ChunkPoly* poly = nullptr;  // delay polynomials, B x (tile points / 16)
+    ChunkPoly* poly = nullptr;  // delay polynomials, B x (tile points / 8)
     size_t poly_stride = 0;
-    int32_t* pok = nullptr;     // per slot: polynomials accurate enough
+    int32_t* pok = nullptr;     // per slot: log2 points per chunk (4 or 3), 0 = exact solve
 };
 
 // Optional per-stage outputs (template slot 0 only).

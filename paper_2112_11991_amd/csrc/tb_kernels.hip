@@ -444,27 +444,30 @@ __global__ __launch_bounds__(NT) void k_tile_series(const float* __restrict__ in
 
 // Delay polynomials of a template, shared by every pass-1 workgroup.  Tile
 // points are grouped in chunks of 16 consecutive points e (row s = e / C1,
-// column c = e % C1); in the tile of column offset c0, point e carries the
-// samples j = 2 (c0 + c + R s) and j + 1.  Chunk g is expanded around the
-// middle sample jmid of its samples in the tile with c0 = 0; a tile with
-// another offset evaluates the same polynomial at u = j - jmid, at most
-// 2 (R - C1) further out, and the accuracy bound covers that full reach.
-// Every chunk spans the same samples, so one flag per template says whether
-// the polynomials are used or the exact per-sample solve.
+// column c = e % C1), or of 8 when 16 would miss the accuracy bound; in the
+// tile of column offset c0, point e carries the samples j = 2 (c0 + c + R s)
+// and j + 1.  Chunk g is expanded around the middle sample jmid of its
+// samples in the tile with c0 = 0; a tile with another offset evaluates the
+// same polynomial at u = j - jmid, at most 2 (R - C1) further out, and the
+// accuracy bound covers that full reach.  Every chunk of a size spans the
+// same samples, so one word per template gives log2 of the chunk size used
+// (4 or 3), or 0 for the exact per-sample solve.
 __global__ __launch_bounds__(NT) void k_chunk_polys(const TmplDev* __restrict__ tm, double tsamp, int R, int C1,
-                                                    int nchunk, ChunkPoly* __restrict__ polys, size_t poly_stride,
+                                                    int npts, ChunkPoly* __restrict__ polys, size_t poly_stride,
                                                     int32_t* __restrict__ pok)
 {
     const int g = (int)(blockIdx.x * NT + threadIdx.x);
     const TmplDev p = tm[blockIdx.y];
     auto jof = [&](int e) -> int { return 2 * (e % C1 + R * (e / C1)); };
-    if (g == 0) {
-        const int lo = jof(0), hi = jof(15) + 1, mid = lo + (hi - lo) / 2;
-        const double U = (double)(hi - mid) + 2.0 * (double)(R - C1);
-        pok[blockIdx.y] = poly_ok(p, tsamp, U) ? 1 : 0;
-    }
-    if (g >= nchunk) return;
-    const int lo = jof(16 * g), hi = jof(16 * g + 15) + 1, mid = lo + (hi - lo) / 2;
+    auto reach = [&](int len) -> double {
+        const int lo = jof(0), hi = jof(len - 1) + 1, mid = lo + (hi - lo) / 2;
+        return (double)(hi - mid) + 2.0 * (double)(R - C1);
+    };
+    const int shift = poly_ok(p, tsamp, reach(16)) ? 4 : poly_ok(p, tsamp, reach(8)) ? 3 : 0;
+    if (g == 0) pok[blockIdx.y] = shift;
+    if (shift == 0 || g >= (npts >> shift)) return;
+    const int len = 1 << shift;
+    const int lo = jof(len * g), hi = jof(len * g + len - 1) + 1, mid = lo + (hi - lo) / 2;
     const DelayPoly d = delay_poly(p, tsamp, mid);
     ChunkPoly c;
     c.c0 = d.c0;
@@ -497,22 +500,23 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
 {
     constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1, RS = S / 16;
     __shared__ __align__(16) float2 lds[C1 * LSP];
-    static_assert(sizeof(ChunkPoly) * T <= sizeof(float2) * C1 * LSP, "polynomials must fit in the tile");
+    static_assert(sizeof(ChunkPoly) * 2 * T <= sizeof(float2) * C1 * LSP, "polynomials must fit in the tile");
     const int tile = xcd_remap(blockIdx.x, R / C1);
     const int c0 = tile * C1;
     const int c = (int)threadIdx.x % C1, row0 = (int)threadIdx.x / C1;
     const uint32_t n32 = (uint32_t)n;
 
-    if (pok[blockIdx.y]) {
+    const int shift = pok[blockIdx.y];  // log2 points per polynomial chunk, 0 = exact solve
+    if (shift) {
         // Sample indices fit in 32 bits: n <= 2^24 and the host bounds the delay.
         // The template's T chunk polynomials are parked in the (not yet used)
         // tile memory, so that their reads wait on LDS only and the series
         // loads of earlier points stay in flight.
         ChunkPoly* cp = reinterpret_cast<ChunkPoly*>(lds);
-        cp[threadIdx.x] = polys[blockIdx.y * poly_stride + threadIdx.x];
+        for (int c = (int)threadIdx.x; c < (C1 * S) >> shift; c += T) cp[c] = polys[blockIdx.y * poly_stride + c];
         __syncthreads();
         auto sources = [&](int i, int& j, int& i0, int& i1) {
-            const ChunkPoly d = cp[((int)threadIdx.x + i * T) >> 4];
+            const ChunkPoly d = cp[((int)threadIdx.x + i * T) >> shift];
             j = 2 * (c0 + c + R * (row0 + RS * i));
             const double u = (double)(j - d.jmid), u1 = u + 1.0;
             const double d0 = d.c0 + u * (d.c1 + u * (d.c2 + u * (d.c3 + u * d.c4)));
@@ -1041,9 +1045,9 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
     hipError_t e;
     const TmplDev* tmw = tm + tmpl_base;
     if (ev && (e = hipEventRecord(ev[K_POLY], s)) != hipSuccess) return e;
-    const int nchunk = (int)(std::min<int64_t>(g.TE, g.M) / 16);
+    const int npts = (int)std::min<int64_t>(g.TE, g.M), nchunk = npts / 8;
     hipLaunchKernelGGL(k_chunk_polys, dim3((nchunk + NT - 1) / NT, nslots), dim3(NT), 0, s, tmw, tsamp, g.R, g.C1,
-                       nchunk, ws.poly, ws.poly_stride, ws.pok);
+                       npts, ws.poly, ws.poly_stride, ws.pok);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[K_PASS1], s)) != hipSuccess) return e;
     if ((e = launch_fft1(g, x, tsamp, tmw, nslots, ws, ins.src, s)) != hipSuccess) return e;

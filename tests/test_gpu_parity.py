@@ -58,6 +58,8 @@ CASES = [
     (17, 64e-6, 4096, (7200.0, 0.5, 1.0, 0.0, 0.0)),
     (18, 64e-6, 4096, (1800.0, 1.5, 5.5, 0.1, 0.7)),
     (19, 64e-6, 2048, (3000.0, 2.0, 0.1, 0.0, 0.0)),
+    # a short orbit whose delay needs the 8-point polynomial chunks at this size
+    (21, 64e-6, 4096, (380.0, 1.5, 2.0, 0.05, 1.0)),
 ]
 
 
