@@ -54,7 +54,9 @@ def workload(name: str, templates: int | None):
     raise SystemExit("unknown workload " + name)
 
 
-DEFAULT_TILE = 8192  # FFT points per workgroup when the plan chooses
+def default_tile(n: int) -> int:
+    """FFT points per workgroup when the plan chooses (mirrors the library)."""
+    return 16384 if n // 2 >= (1 << 23) else 8192
 
 
 def describe(w, name):
@@ -180,9 +182,11 @@ def run_bank(args, tb, torch):
     """c1/c2/c3/c4: every series x the whole bank per step."""
     w = workload(args.workload, args.templates)
     conf = describe(w, args.workload)
-    conf["tile_points"] = args.tile or DEFAULT_TILE
+    conf["tile_points"] = args.tile or default_tile(max(int(x.size) for x in w.series))
     conf["requests_per_series"] = max(1, args.split)
-    lanes = args.lanes or 4
+    # one series: waves of one stream keep the device busy (lanes add no throughput there);
+    # several series: one request per series, spread over four lanes
+    lanes = args.lanes or (4 if len(w.series) > 1 else 1)
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
                    threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18,
                    tile_points=args.tile)

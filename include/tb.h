@@ -66,7 +66,8 @@ typedef struct {
                                   lanes overlaps on the device.  Lane 0 is `stream`. */
     uint32_t flags;            /* reserved, 0 */
     uint32_t tile_points;      /* FFT points per workgroup: 8192 (two workgroups per compute
-                                  unit) or 16384 (one); 0 = the plan's choice (8192) */
+                                  unit) or 16384 (one); 0 = the plan's choice (8192, and
+                                  16384 for series of 2^24 samples) */
 } tb_config;
 
 /* One Keplerian orbital template (Sec. 2.1): P_orb = 2 pi / Omega, tau = a sin(eps)/c,

@@ -251,7 +251,9 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     g.log2n = log2n;
     g.n = (int64_t)1 << log2n;
     g.M = g.n / 2;
-    g.TE = p->cfg.tile_points ? (int)p->cfg.tile_points : 8192;
+    // 8192-point tiles (two workgroups per CU) up to 2^23 samples; at 2^24 they
+    // would leave pass 2 with 8-column workgroups and 32-byte reads
+    g.TE = p->cfg.tile_points ? (int)p->cfg.tile_points : (g.M >= ((int64_t)1 << 23) ? 16384 : 8192);
     const int64_t TE = std::min<int64_t>(g.TE, g.M);
     g.R = (int)std::max<int64_t>(16, g.M / g.TE);
     g.S = (int)(g.M / g.R);
@@ -292,7 +294,7 @@ void free_geometry(GeoRec& r)
 int default_batch(const tb_plan_t p, int64_t M)
 {
     if (p->cfg.batch_templates) return (int)p->cfg.batch_templates;
-    int64_t b = ((int64_t)1 << 24) / M;
+    int64_t b = ((int64_t)1 << 25) / M;
     return (int)std::min<int64_t>(256, std::max<int64_t>(4, b));
 }
 
