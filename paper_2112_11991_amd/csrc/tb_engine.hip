@@ -177,7 +177,7 @@ struct tb_plan_s {
     double* d_partial = nullptr;
     uint32_t prof_every = 0;                           // time every k-th wave; 0 = off
     uint64_t prof_wave = 0;                            // waves queued since profiling started
-    std::vector<std::vector<hipEvent_t>> prof_events;  // K_CLASSES + 1 per timed wave
+    std::vector<Marks> prof_events;                    // marks of every timed wave
     uint64_t prof_templates = 0;
 };
 
@@ -309,11 +309,14 @@ tb_status get_slots(tb_plan_t p, int lane, const Geometry& g, Slots** out)
     SlotRec rec;
     Slots& s = rec.s;
     s.B = default_batch(p, g.M);
+    // passes 1 and 2 in groups whose exchange buffer (8M bytes per template)
+    // stays within about 128 MiB, so that pass 2 reads it from the cache
+    s.BY = (int)std::max<int64_t>(1, std::min<int64_t>(s.B, ((int64_t)1 << 24) / g.M));
     s.y_stride = (size_t)g.M;
     s.p_stride = ((size_t)g.M + 1 + 63) & ~(size_t)63;
     s.med_stride = ((size_t)g.nblk + 63) & ~(size_t)63;
     s.poly_stride = (size_t)std::min<int64_t>(g.TE, g.M) / 8;
-    size_t by = sizeof(float2) * s.y_stride * s.B, bp = sizeof(float) * s.p_stride * s.B,
+    size_t by = sizeof(float2) * s.y_stride * s.BY, bp = sizeof(float) * s.p_stride * s.B,
            bm = sizeof(float) * s.med_stride * s.B, bq = sizeof(ChunkPoly) * s.poly_stride * s.B,
            bk = sizeof(int32_t) * (size_t)s.B;
     rec.bytes = by + bp + bm + bq + bk;
@@ -404,16 +407,13 @@ tb_status enqueue(tb_plan_t p, const Crew& crew, const SeriesRec& sr, Geometry* 
         Slots* ws = crew.slots[wave % nc];
         hipStream_t stream = crew.streams[wave % nc];
         int nslots = (int)std::min<uint32_t>((uint32_t)ws->B, count - w0);
-        hipEvent_t* ev = nullptr;
+        Marks* marks = nullptr;
         if (p->prof_every && p->prof_wave++ % p->prof_every == 0) {
-            std::vector<hipEvent_t> evs(K_CLASSES + 1, nullptr);
-            for (auto& e : evs)
-                if (hipEventCreate(&e) != hipSuccess) return TB_ERR_DEVICE;
-            p->prof_events.push_back(std::move(evs));
-            ev = p->prof_events.back().data();
+            p->prof_events.emplace_back();
+            marks = &p->prof_events.back();
             p->prof_templates += (uint64_t)nslots;
         }
-        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, pp, ring, counter, ins, stream, ev) !=
+        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, pp, ring, counter, ins, stream, marks) !=
             hipSuccess)
             return TB_ERR_DEVICE;
         w0 += (uint32_t)nslots;
@@ -600,7 +600,7 @@ tb_status tb_destroy(tb_plan_t p)
             for (auto& kv : L.slots) free_slots(kv.second.s);
         for (auto& kv : p->geo) free_geometry(kv.second);
         for (auto& v : p->prof_events)
-            for (auto e : v) hipEventDestroy(e);
+            for (auto& m : v) hipEventDestroy(m.second);
         hipFree(p->d_partial);
         hipStreamDestroy(p->copy_stream);
         for (auto& L : p->lanes)
@@ -919,7 +919,7 @@ tb_status tb_profile(tb_plan_t p, int every)
         TB_TRY(hipSetDevice(p->cfg.device));
         TB_TRY(sync_lanes(p));
         for (auto& v : p->prof_events)
-            for (auto e : v) hipEventDestroy(e);
+            for (auto& m : v) hipEventDestroy(m.second);
         p->prof_events.clear();
         p->prof_templates = 0;
         p->prof_wave = 0;
@@ -935,15 +935,19 @@ tb_status tb_profile_read(tb_plan_t p, double ms[6], uint64_t launches[6], uint6
     TB_TRY(hipSetDevice(p->cfg.device));
     TB_TRY(sync_lanes(p));
     double acc[K_CLASSES] = {0, 0, 0, 0, 0, 0};
+    uint64_t cnt[K_CLASSES] = {0, 0, 0, 0, 0, 0};
     for (auto& v : p->prof_events)
-        for (int k = 0; k < K_CLASSES; ++k) {
+        for (size_t i = 0; i + 1 < v.size(); ++i) {
+            const int k = v[i].first;
+            if (k < 0 || k >= K_CLASSES) continue;
             float f = 0.0f;
-            TB_TRY(hipEventElapsedTime(&f, v[k], v[k + 1]));
+            TB_TRY(hipEventElapsedTime(&f, v[i].second, v[i + 1].second));
             acc[k] += f;
+            cnt[k] += 1;
         }
     for (int k = 0; k < K_CLASSES; ++k) {
         if (ms) ms[k] = acc[k];
-        if (launches) launches[k] = p->prof_events.size();
+        if (launches) launches[k] = cnt[k];
     }
     if (templates) *templates = p->prof_templates;
     return TB_OK;

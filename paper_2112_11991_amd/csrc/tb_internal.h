@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+#include <vector>
+
 #include "../../include/tb.h"
 
 namespace tb {
@@ -63,8 +66,9 @@ struct PeakParams {
 
 // Device workspace for B templates in flight at one series length.
 struct Slots {
-    int B = 0;
-    float2* Y = nullptr;   // exchange buffer, B x M complex
+    int B = 0;             // templates per wave (power, medians, harmonic sum)
+    int BY = 0;            // exchange slots: passes 1 and 2 run in groups of BY templates
+    float2* Y = nullptr;   // exchange buffer, BY x M complex
     size_t y_stride = 0;   // complex per slot
     float* P = nullptr;    // power, B x (M + 1), padded
     size_t p_stride = 0;
@@ -87,12 +91,16 @@ hipError_t launch_mean_subtract(const float* in, float* out, int64_t n, double* 
 // Kernel classes timed by the plan's profiler, in launch order.
 enum { K_POLY = 0, K_PASS1 = 1, K_PASS2 = 2, K_MEDIAN = 3, K_WHITEN = 4, K_HARMSUM = 5, K_CLASSES = 6 };
 
-// Queues the kernels of one wave of nslots templates.  ev, if not null, holds
-// K_CLASSES + 1 events recorded before, between and after them (event k
-// before class k, event K_CLASSES after the last).
+// Timing marks of one wave: (kernel class, event recorded before its kernel),
+// closed by (-1, event after the last kernel).
+using Marks = std::vector<std::pair<int, hipEvent_t>>;
+
+// Queues the kernels of one wave of nslots templates (passes 1 and 2 in
+// groups of ws.BY, so that a group's exchange buffer is still cached when
+// pass 2 reads it).  With marks, an event is recorded before every kernel.
 hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
                        int nslots, const Slots& ws, const PeakParams& pp, uint4* ring, uint32_t* counter,
-                       const Inspect& ins, hipStream_t s, hipEvent_t* ev = nullptr);
+                       const Inspect& ins, hipStream_t s, Marks* marks = nullptr);
 hipError_t launch_copy(float4* dst, const float4* src, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
 // Rewrites a mean-removed series into the tile order pass 1 reads.

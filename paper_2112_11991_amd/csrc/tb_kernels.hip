@@ -1040,24 +1040,40 @@ hipError_t launch_copy(float4* dst, const float4* src, size_t count, hipStream_t
 
 hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
                        int nslots, const Slots& ws, const PeakParams& pp, uint4* ring, uint32_t* counter,
-                       const Inspect& ins, hipStream_t s, hipEvent_t* ev)
+                       const Inspect& ins, hipStream_t s, Marks* marks)
 {
     hipError_t e;
+    auto mark = [&](int cls) -> hipError_t {
+        if (!marks) return hipSuccess;
+        hipEvent_t ev = nullptr;
+        hipError_t r = hipEventCreate(&ev);
+        if (r != hipSuccess) return r;
+        marks->emplace_back(cls, ev);
+        return hipEventRecord(ev, s);
+    };
     const TmplDev* tmw = tm + tmpl_base;
-    if (ev && (e = hipEventRecord(ev[K_POLY], s)) != hipSuccess) return e;
+    if ((e = mark(K_POLY)) != hipSuccess) return e;
     const int npts = (int)std::min<int64_t>(g.TE, g.M), nchunk = npts / 8;
     hipLaunchKernelGGL(k_chunk_polys, dim3((nchunk + NT - 1) / NT, nslots), dim3(NT), 0, s, tmw, tsamp, g.R, g.C1,
                        npts, ws.poly, ws.poly_stride, ws.pok);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[K_PASS1], s)) != hipSuccess) return e;
-    if ((e = launch_fft1(g, x, tsamp, tmw, nslots, ws, ins.src, s)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[K_PASS2], s)) != hipSuccess) return e;
-    if ((e = launch_fft2(g, nslots, ws, s)) != hipSuccess) return e;
+    for (int q0 = 0; q0 < nslots; q0 += ws.BY) {
+        const int nq = std::min(ws.BY, nslots - q0);
+        Slots grp = ws;
+        grp.poly = ws.poly + (size_t)q0 * ws.poly_stride;
+        grp.pok = ws.pok + q0;
+        grp.P = ws.P + (size_t)q0 * ws.p_stride;
+        int32_t* src = q0 == 0 ? ins.src : nullptr;
+        if ((e = mark(K_PASS1)) != hipSuccess) return e;
+        if ((e = launch_fft1(g, x, tsamp, tmw + q0, nq, grp, src, s)) != hipSuccess) return e;
+        if ((e = mark(K_PASS2)) != hipSuccess) return e;
+        if ((e = launch_fft2(g, nq, grp, s)) != hipSuccess) return e;
+    }
     if (ins.power &&
         (e = hipMemcpyAsync(ins.power, ws.P, sizeof(float) * (size_t)(g.M + 1), hipMemcpyDeviceToDevice, s)) !=
             hipSuccess)
         return e;
-    if (ev && (e = hipEventRecord(ev[K_MEDIAN], s)) != hipSuccess) return e;
+    if ((e = mark(K_MEDIAN)) != hipSuccess) return e;
     if (g.W <= 16 * NT)
         hipLaunchKernelGGL((k_median<16>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
                            ws.med, ws.med_stride);
@@ -1065,11 +1081,11 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
         hipLaunchKernelGGL((k_median<32>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
                            ws.med, ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[K_WHITEN], s)) != hipSuccess) return e;
+    if ((e = mark(K_WHITEN)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk, ws.med,
                        ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[K_HARMSUM], s)) != hipSuccess) return e;
+    if ((e = mark(K_HARMSUM)) != hipSuccess) return e;
     int ntile = (int)((g.M + 1 + HT - 1) / HT);
     dim3 hg(ntile, nslots);
     switch (pp.nfold) {
@@ -1081,8 +1097,7 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
     default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[K_CLASSES], s)) != hipSuccess) return e;
-    return hipSuccess;
+    return mark(-1);
 }
 
 }  // namespace tb
