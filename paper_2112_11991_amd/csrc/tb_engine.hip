@@ -239,6 +239,40 @@ std::vector<float2> stage_twiddles(int ns_max)
     return t;
 }
 
+// Harmonic-sum tile order for a grid of ntile rounded up to a multiple of 8
+// workgroups (workgroup x runs on XCD x % 8): binary subtrees of tiles
+// {r, 2r, 2r+1, 4r, ...}, r in [2^a, 2^(a+1)) with about 64 tiles per tree,
+// go whole to one XCD in breadth-first order (a tile's parent before it);
+// tiles below 2^a are spread round robin.
+std::vector<int32_t> harmsum_order(int ntile)
+{
+    const int X = 8;
+    std::vector<std::vector<int32_t>> q(X);
+    int a = 3;  // at least 8 roots
+    while ((2 << a) * 64 <= ntile) ++a;  // roots [2^a, 2^(a+1)): trees of ~64 tiles
+    const int r0 = 1 << a;
+    int next = 0;
+    for (int r = r0; r < 2 * r0 && r < ntile; ++r) {
+        std::vector<int32_t>& dst = q[next];
+        next = (next + 1) % X;
+        for (int64_t lo = r, width = 1; lo < ntile; lo *= 2, width *= 2)
+            for (int64_t t = lo; t < lo + width && t < ntile; ++t) dst.push_back((int32_t)t);
+    }
+    for (int t = 0; t < r0 && t < ntile; ++t) {
+        // the shortest queue takes the next low tile
+        int best = 0;
+        for (int c = 1; c < X; ++c)
+            if (q[c].size() < q[best].size()) best = c;
+        q[best].push_back(t);
+    }
+    size_t longest = 0;
+    for (auto& v : q) longest = std::max(longest, v.size());
+    std::vector<int32_t> tile_of(longest * X, -1);
+    for (int c = 0; c < X; ++c)
+        for (size_t k = 0; k < q[c].size(); ++k) tile_of[k * X + c] = q[c][k];
+    return tile_of;
+}
+
 tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
 {
     auto it = p->geo.find(log2n);
@@ -266,6 +300,14 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     int64_t hi = std::max<int64_t>(1, g.M >> TW_LO_BITS);
     std::vector<float2> v;
     tb_status st;
+    {
+        std::vector<int32_t> order = harmsum_order((int)((g.M + 1 + g.htile - 1) / g.htile));
+        size_t b = order.size() * sizeof(int32_t);
+        g.hgrid = (int)order.size();
+        if (hipMalloc(&g.tile_of, b) != hipSuccess) return TB_ERR_OOM;
+        TB_TRY(hipMemcpy(g.tile_of, order.data(), b, hipMemcpyHostToDevice));
+        rec.bytes += b;
+    }
     v = stage_twiddles(std::max(2, std::max(g.S, g.R) / 16));
     if ((st = upload_table(v, &g.twst, &rec.bytes))) return st;
     v = twiddles(1 << TW_LO_BITS, 1.0, (double)g.M);
@@ -285,6 +327,7 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
 void free_geometry(GeoRec& r)
 {
     hipFree(r.g.twst);
+    hipFree(r.g.tile_of);
     hipFree(r.g.twM_lo);
     hipFree(r.g.twM_hi);
     hipFree(r.g.tw2M_lo);

@@ -38,6 +38,8 @@ struct Geometry {
     float2* twst = nullptr;                        // radix-16 stage twiddles, every stride
     float2* twM_lo = nullptr, *twM_hi = nullptr;   // W_M^q split in 2^10 x rest
     float2* tw2M_lo = nullptr, *tw2M_hi = nullptr; // W_2M^k likewise
+    int32_t* tile_of = nullptr;                    // harmonic-sum tile per workgroup (XCD-aware order)
+    int hgrid = 0;                                 // harmonic-sum workgroups per template (multiple of 8)
 };
 
 constexpr int TW_LO_BITS = 10;

@@ -871,13 +871,20 @@ __device__ __forceinline__ void fold_sums(const float* __restrict__ Ps, int kt, 
     }
 }
 
+// Tile order: the grid's x extent is a multiple of 8, so workgroup x runs on
+// XCD x % 8, and tile_of[x] is the tile it takes (-1: none).  The table puts
+// each binary subtree {t, 2t, 2t+1, 4t, ...} of tiles on one XCD, parent
+// first: runs j <= 8 of tiles 2t and 2t+1 lie inside run 2j of tile t, so
+// they are read while still in that XCD's L2.
 template <int NF>
 __global__ __launch_bounds__(NT) void k_harmsum(const float* __restrict__ P, size_t p_stride, int64_t M,
                                                 int tmpl_base, PeakParams pp, uint4* __restrict__ ring,
-                                                uint32_t* __restrict__ counter, float* __restrict__ sums_out)
+                                                uint32_t* __restrict__ counter, float* __restrict__ sums_out,
+                                                const int32_t* __restrict__ tile_of)
 {
     constexpr int R4 = HT / NT;
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = tile_of[blockIdx.x];
+    if (tile < 0) return;
     const int k0 = tile * HT;
     const int Mi = (int)M;
     const int kend = k0 + HT - 1 < Mi ? k0 + HT - 1 : Mi;
@@ -1086,14 +1093,13 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
                        ws.med_stride);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = mark(K_HARMSUM)) != hipSuccess) return e;
-    int ntile = (int)((g.M + 1 + HT - 1) / HT);
-    dim3 hg(ntile, nslots);
+    dim3 hg(g.hgrid, nslots);
     switch (pp.nfold) {
-    case 1: hipLaunchKernelGGL((k_harmsum<1>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
-    case 2: hipLaunchKernelGGL((k_harmsum<2>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
-    case 3: hipLaunchKernelGGL((k_harmsum<3>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
-    case 4: hipLaunchKernelGGL((k_harmsum<4>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
-    case 5: hipLaunchKernelGGL((k_harmsum<5>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums); break;
+    case 1: hipLaunchKernelGGL((k_harmsum<1>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 2: hipLaunchKernelGGL((k_harmsum<2>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 3: hipLaunchKernelGGL((k_harmsum<3>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 4: hipLaunchKernelGGL((k_harmsum<4>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 5: hipLaunchKernelGGL((k_harmsum<5>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
     default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
