@@ -223,19 +223,22 @@ std::vector<float2> twiddles(int64_t count, double num, double den)
     return t;
 }
 
-// Radix-16 stage twiddles W_{16 NS}^{r k}, r = 1..15, for k < NS and every
-// stride NS = 2, 4, ..., ns_max, in the order the kernels index them (the
-// table of a longer transform extends that of a shorter one).
+// Radix-16 stage twiddles, in the order the kernels index them: for strides
+// NS = 2..16 a record of W_{16 NS}^{r k}, r = 1..15, per k < NS (450 entries
+// in all, zero-padded), then for NS = 32..ns_max the powers W_{16 NS}^i,
+// i < 16 NS (the table of a longer transform extends that of a shorter one).
 std::vector<float2> stage_twiddles(int ns_max)
 {
+    auto w = [](double num, double den) {
+        double a = -2.0 * kPi * num / den;
+        return make_float2((float)std::cos(a), (float)std::sin(a));
+    };
     std::vector<float2> t;
-    t.reserve(15 * (2 * (size_t)ns_max));
-    for (int ns = 2; ns <= ns_max; ns *= 2)
+    for (int ns = 2; ns <= 16; ns *= 2)
         for (int k = 0; k < ns; ++k)
-            for (int r = 1; r < 16; ++r) {
-                double a = -2.0 * kPi * (double)(r * k) / (16.0 * ns);
-                t.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
-            }
+            for (int r = 1; r < 16; ++r) t.push_back(ns <= ns_max ? w((double)(r * k), 16.0 * ns) : make_float2(0, 0));
+    for (int ns = 32; ns <= ns_max; ns *= 2)
+        for (int i = 0; i < 16 * ns; ++i) t.push_back(w((double)i, 16.0 * ns));
     return t;
 }
 

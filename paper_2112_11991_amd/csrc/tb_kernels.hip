@@ -253,6 +253,13 @@ __device__ __forceinline__ void dft<16>(float2* v)
 // only on NS, so one table serves every transform length.
 __device__ __forceinline__ constexpr int twst_offset(int NS) { return 15 * (NS - 2); }
 
+// From stride 32 on, lanes hold so many different k that per-k records would
+// spread a wave's load over tens of cache lines; those stages read W^k, W^2k,
+// W^4k and W^8k from a table of W_{16 NS}^i (i < 16 NS, consecutive i) and
+// form the other eleven powers by products (at most three roundings deep).
+constexpr int TWST_RECORDS = 15 * (2 + 4 + 8 + 16);  // record tables of NS = 2..16
+__device__ __forceinline__ constexpr int twpow_offset(int NS) { return TWST_RECORDS + 16 * (NS - 32); }
+
 // One Stockham stage.  Element addresses are pidx(a) + pidx(b) with a < b's
 // stride (both powers of two), which equals pidx(a + b); writing them that way
 // leaves one address per butterfly and compile-time offsets for the rest.
@@ -269,10 +276,25 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
         const float2* src = lds + c * LSP + pidx(j);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) v[u * RAD + r] = src[pidx(r * LR)];
-        if (NS > 1) {
+        if (NS > 1 && NS < 32) {
             const float2* tw = twst + twst_offset(NS) + 15 * k;
 #pragma unroll
             for (int r = 1; r < RAD; ++r) v[u * RAD + r] = cmul(v[u * RAD + r], tw[r - 1]);
+        } else if (NS >= 32) {
+            const float2* T = twst + twpow_offset(NS);
+            float2 w[16];
+            w[1] = T[k];
+            w[2] = T[2 * k];
+            w[4] = T[4 * k];
+            w[8] = T[8 * k];
+            w[3] = cmul(w[1], w[2]);
+            w[5] = cmul(w[1], w[4]);
+            w[6] = cmul(w[2], w[4]);
+            w[7] = cmul(w[3], w[4]);
+#pragma unroll
+            for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+#pragma unroll
+            for (int r = 1; r < RAD; ++r) v[u * RAD + r] = cmul(v[u * RAD + r], w[r]);
         }
         dft<RAD>(v + u * RAD);
     }
