@@ -604,11 +604,10 @@ __device__ __forceinline__ float power_of(float2 z, float2 zm, float2 w)
 // (in column 0 at (R - k1) mod R).  Each slot emits |X|^2 for its own bins:
 // runs of D consecutive bins per k1, ascending for A, descending for mirrors.
 //
-// With R > 16 every pass-1 workgroup held one column (C1 = 1); thread t then
-// loads slot q = t % D2 of blocks w = t / D2 + RK i and emits bins
-// k1 = t / D2 + RK i of that slot, so all of its addresses are a per-thread
-// base plus compile-time steps.  R = 16 (short series) takes the general
-// index arithmetic.
+// When every pass-1 workgroup held one column (C1 = 1, R > 16), thread t
+// loads slot q = t % D2 of blocks w = t / D2 + RK i, so all of its addresses
+// are a per-thread base plus compile-time steps; other geometries take the
+// general index arithmetic.  Thread t emits bins k1 = t / D2 + RK i of slot q.
 template <int R, int D2>
 __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__ Y, size_t y_stride, int S, int lgS,
                                                       int lgC1, float* __restrict__ P, size_t p_stride, int64_t M,
@@ -617,7 +616,8 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
                                                       const float2* __restrict__ tw2M_hi)
 {
     constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2, RK = R / 16, LD2 = Log2<D2>::value;
-    constexpr bool ONE_COLUMN = R > 16;
+    // R > 16 with one pass-1 column per workgroup (the plan's geometries)
+    const bool one_column = R > 16 && lgC1 == 0;
     __shared__ float2 lds[D2 * LSP];
     const int g = xcd_remap(blockIdx.x, S / D2);
     const float2* Ys = Y + blockIdx.y * y_stride;
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
     const int a = g * D + (q < D ? q : q - D);
     const int col = q < D ? a : (a == 0 ? S / 2 : S - a);
 
-    if constexpr (ONE_COLUMN) {
+    if (one_column) {
         // element i: block w = k1t + RK i, column col
         const uint32_t off0 = ((((uint32_t)k1t << lgS) + (uint32_t)col) << 3);
         const uint32_t step = (uint32_t)RK << (lgS + 3);
