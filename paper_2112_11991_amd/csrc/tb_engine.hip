@@ -252,7 +252,7 @@ std::vector<int32_t> harmsum_order(int ntile)
     const int X = 8;
     std::vector<std::vector<int32_t>> q(X);
     int a = 3;  // at least 8 roots
-    while ((2 << a) * 64 <= ntile) ++a;  // roots [2^a, 2^(a+1)): trees of ~64 tiles
+    while ((2 << a) * 64 <= ntile) ++a;  // roots [2^a, 2^(a+1)): trees of ~64 tiles (best of 16..256)
     const int r0 = 1 << a;
     int next = 0;
     for (int r = r0; r < 2 * r0 && r < ntile; ++r) {
