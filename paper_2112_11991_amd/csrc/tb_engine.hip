@@ -340,7 +340,7 @@ void free_geometry(GeoRec& r)
 int default_batch(const tb_plan_t p, int64_t M)
 {
     if (p->cfg.batch_templates) return (int)p->cfg.batch_templates;
-    int64_t b = ((int64_t)1 << 25) / M;
+    int64_t b = ((int64_t)1 << 26) / M;
     return (int)std::min<int64_t>(256, std::max<int64_t>(4, b));
 }
 
