@@ -51,6 +51,7 @@ class Config(C.Structure):
         ("threshold_sigma", C.c_double),
         ("fmin_hz", C.c_double),
         ("fmax_hz", C.c_double),
+        ("series_whitening", C.c_int32),
     ]
 
 
@@ -142,6 +143,8 @@ def _bind(L):
     L.tbo_fft.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     L.tbo_power.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
     L.tbo_whiten.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]
+    L.tbo_series_levels.argtypes = [C.c_void_p, P(Config), C.c_void_p, C.c_void_p]
+    L.tbo_series_levels.restype = C.c_int
     L.tbo_harmsum.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
     L.tbo_threshold.argtypes = [C.c_int32, C.c_double]
     L.tbo_threshold.restype = C.c_double
@@ -185,9 +188,10 @@ def _templates_array(templates) -> np.ndarray:
     return arr
 
 
-def config(n, tsamp, harm_max=16, whiten_window=4096, threshold_sigma=6.0, fmin_hz=1.0, fmax_hz=0.0) -> Config:
+def config(n, tsamp, harm_max=16, whiten_window=4096, threshold_sigma=6.0, fmin_hz=1.0, fmax_hz=0.0,
+           series_whitening=False) -> Config:
     return Config(int(n), float(tsamp), int(harm_max), int(whiten_window), float(threshold_sigma),
-                  float(fmin_hz), float(fmax_hz))
+                  float(fmin_hz), float(fmax_hz), int(bool(series_whitening)))
 
 
 def mean_subtract(x: np.ndarray) -> np.ndarray:
@@ -258,6 +262,19 @@ def whiten(p: np.ndarray, w: int):
     phat = np.empty(nb)
     lib().tbo_whiten(_ptr(p), nb, int(w), _ptr(med), _ptr(phat))
     return phat, med
+
+
+def series_levels(x0: np.ndarray, cfg: Config):
+    """Whitening taken once from the series' own spectrum: (medians, level
+    per bin k = 0..n/2, level[0] = 0)."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float32)
+    nb = cfg.n // 2 + 1
+    nblk = (nb - 1 + cfg.whiten_window - 1) // cfg.whiten_window
+    med = np.empty(nblk)
+    lev = np.empty(nb)
+    if lib().tbo_series_levels(_ptr(x0), C.byref(cfg), _ptr(med), _ptr(lev)) != 0:
+        raise ValueError("tbo_series_levels failed")
+    return med, lev
 
 
 def harmsum(phat: np.ndarray, harm_max: int = 16) -> np.ndarray:

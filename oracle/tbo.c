@@ -186,7 +186,9 @@ static int cmp_double(const void* a, const void* b)
  * first and last centre.  The whitened power is P_k ln2 / m(k), so that noise
  * powers have median ln 2 and mean 1, i.e. follow the exponential law behind
  * the chi^2 statistics of Sec. 2.1.  The DC bin is set to zero. */
-void tbo_whiten(const double* p, int64_t nbins, int64_t w, double* med, double* phat)
+/* The whitening level m(k) of every bin k >= 1 (lev[0] = 0): block medians
+ * of p, joined by straight lines between block centres. */
+static void whiten_levels(const double* p, int64_t nbins, int64_t w, double* med, double* lev)
 {
     int64_t m = nbins - 1; /* bins 1..m */
     int64_t nb = (m + w - 1) / w;
@@ -202,7 +204,7 @@ void tbo_whiten(const double* p, int64_t nbins, int64_t w, double* med, double* 
         cent[b] = (double)start + (double)(cnt - 1) / 2.0;
         if (med) med[b] = meds[b];
     }
-    phat[0] = 0.0;
+    lev[0] = 0.0;
     int64_t b = 0;
     for (int64_t k = 1; k < nbins; ++k) {
         double level;
@@ -216,11 +218,54 @@ void tbo_whiten(const double* p, int64_t nbins, int64_t w, double* med, double* 
             double f = (kk - cent[b]) / (cent[b + 1] - cent[b]);
             level = meds[b] + (meds[b + 1] - meds[b]) * f;
         }
-        phat[k] = (level > 0.0) ? p[k] * M_LN2 / level : 0.0;
+        lev[k] = level;
     }
     free(meds);
     free(cent);
     free(tmp);
+}
+
+/* P^_k = P_k ln2 / m(k) for k >= 1 (0 where m(k) is not positive), P^_0 = 0. */
+static void whiten_apply(const double* p, int64_t nbins, const double* lev, double* phat)
+{
+    phat[0] = 0.0;
+    for (int64_t k = 1; k < nbins; ++k) {
+        double level = lev[k];
+        phat[k] = (level > 0.0) ? p[k] * M_LN2 / level : 0.0;
+    }
+}
+
+void tbo_whiten(const double* p, int64_t nbins, int64_t w, double* med, double* phat)
+{
+    double* lev = (double*)malloc(sizeof(double) * (size_t)nbins);
+    whiten_levels(p, nbins, w, med, lev);
+    whiten_apply(p, nbins, lev, phat);
+    free(lev);
+}
+
+/* O7, once per series: the levels come from the spectrum of the mean-removed
+ * series as loaded (no demodulation, y_j = x0_j) and serve every template
+ * searched on it. */
+int tbo_series_levels(const float* x0, const tbo_config* cfg, double* med, double* lev)
+{
+    int64_t n = cfg->n, nb = n / 2 + 1;
+    double* y = (double*)malloc(sizeof(double) * (size_t)n);
+    double* re = (double*)malloc(sizeof(double) * (size_t)nb);
+    double* im = (double*)malloc(sizeof(double) * (size_t)nb);
+    double* p = (double*)malloc(sizeof(double) * (size_t)nb);
+    int rc = (y && re && im && p) ? 0 : -1;
+    if (rc == 0) {
+        for (int64_t j = 0; j < n; ++j) y[j] = (double)x0[j];
+        if (n <= 4096) tbo_dft_naive(y, n, re, im);
+        else tbo_fft(y, n, re, im);
+        tbo_power(re, im, nb, p);
+        whiten_levels(p, nb, cfg->whiten_window, med, lev);
+    }
+    free(y);
+    free(re);
+    free(im);
+    free(p);
+    return rc;
 }
 
 /* ---------------------------------------------------------------- O8 ---- */
@@ -344,11 +389,15 @@ static int valid_cfg(const tbo_config* c)
     if (c->harm_max != 1 && c->harm_max != 2 && c->harm_max != 4 && c->harm_max != 8
         && c->harm_max != 16)
         return 0;
+    if (c->series_whitening != 0 && c->series_whitening != 1) return 0;
     return 1;
 }
 
-/* Demodulate, transform, power and whiten one template. */
-static void front_end(const float* x0, const tbo_config* c, const tbo_template* t, work_t* w)
+/* Demodulate, transform, power and whiten one template: with series levels
+ * (lev non-NULL) those are applied, otherwise the template's own block
+ * medians (into med, may be NULL). */
+static void front_end(const float* x0, const tbo_config* c, const tbo_template* t, const double* lev,
+                      double* med, work_t* w)
 {
     int64_t n = c->n, nb = n / 2 + 1;
     tbo_resample_index(t, n, c->tsamp, NULL, w->src);
@@ -356,7 +405,8 @@ static void front_end(const float* x0, const tbo_config* c, const tbo_template* 
     if (n <= 4096) tbo_dft_naive(w->y, n, w->re, w->im);
     else tbo_fft(w->y, n, w->re, w->im);
     tbo_power(w->re, w->im, nb, w->p);
-    tbo_whiten(w->p, nb, c->whiten_window, NULL, w->phat);
+    if (lev) whiten_apply(w->p, nb, lev, w->phat);
+    else tbo_whiten(w->p, nb, c->whiten_window, med, w->phat);
 }
 
 int tbo_template_stages(const float* x0, const tbo_config* cfg, const tbo_template* t,
@@ -365,21 +415,19 @@ int tbo_template_stages(const float* x0, const tbo_config* cfg, const tbo_templa
     if (!valid_cfg(cfg)) return -1;
     int64_t n = cfg->n, nb = n / 2 + 1;
     work_t w;
-    if (work_alloc(&w, n)) {
+    double* lev = cfg->series_whitening ? (double*)malloc(sizeof(double) * (size_t)nb) : NULL;
+    if (work_alloc(&w, n) || (cfg->series_whitening && (!lev || tbo_series_levels(x0, cfg, med, lev)))) {
         work_free(&w);
+        free(lev);
         return -1;
     }
-    tbo_resample_index(t, n, cfg->tsamp, NULL, w.src);
-    tbo_resample(x0, n, w.src, w.y);
-    if (n <= 4096) tbo_dft_naive(w.y, n, w.re, w.im);
-    else tbo_fft(w.y, n, w.re, w.im);
-    tbo_power(w.re, w.im, nb, w.p);
-    tbo_whiten(w.p, nb, cfg->whiten_window, med, w.phat);
+    front_end(x0, cfg, t, lev, lev ? NULL : med, &w);
     if (src) memcpy(src, w.src, sizeof(int64_t) * (size_t)n);
     if (p) memcpy(p, w.p, sizeof(double) * (size_t)nb);
     if (phat) memcpy(phat, w.phat, sizeof(double) * (size_t)nb);
     if (s) tbo_harmsum(w.phat, nb, cfg->harm_max, s);
     work_free(&w);
+    free(lev);
     return 0;
 }
 
@@ -405,6 +453,7 @@ typedef struct {
     const float* x0;
     const tbo_config* cfg;
     const tbo_template* t;
+    const double* lev; /* series levels, or NULL for per-template whitening */
     uint32_t count, first_id, series_id;
     double thr[5];
     int64_t kmin;
@@ -468,7 +517,7 @@ static void* worker(void* arg)
     for (;;) {
         int64_t i = __atomic_fetch_add(&J->next, 1, __ATOMIC_SEQ_CST);
         if (i >= (int64_t)J->count) break;
-        front_end(J->x0, J->cfg, &J->t[i], &w);
+        front_end(J->x0, J->cfg, &J->t[i], J->lev, NULL, &w);
         if (pick(J, &w, (uint32_t)i)) __atomic_store_n(&J->failed, 1, __ATOMIC_SEQ_CST);
     }
     work_free(&w);
@@ -492,8 +541,20 @@ int tbo_search(const float* x0, const tbo_config* cfg, const tbo_template* t,
     double T = (double)cfg->n * cfg->tsamp;
     J.kmin = (int64_t)ceil(cfg->fmin_hz * T);
     if (J.kmin < 1) J.kmin = 1;
+    double* lev = NULL;
+    if (cfg->series_whitening) {
+        lev = (double*)malloc(sizeof(double) * (size_t)(cfg->n / 2 + 1));
+        if (!lev || tbo_series_levels(x0, cfg, NULL, lev)) {
+            free(lev);
+            return -1;
+        }
+        J.lev = lev;
+    }
     J.lists = (cand_list*)calloc(count ? count : 1, sizeof(cand_list));
-    if (!J.lists) return -1;
+    if (!J.lists) {
+        free(lev);
+        return -1;
+    }
     if (nthreads < 1) nthreads = 1;
     if ((uint32_t)nthreads > count && count > 0) nthreads = (int32_t)count;
     pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)nthreads);
@@ -512,6 +573,7 @@ int tbo_search(const float* x0, const tbo_config* cfg, const tbo_template* t,
         free(J.lists[i].v);
     }
     free(J.lists);
+    free(lev);
     *n_total = tot;
     return J.failed ? -1 : 0;
 }

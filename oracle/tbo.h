@@ -23,7 +23,8 @@
  *   O7 whitening ............ "Fourier de-reddening", Sec. 5.2 / App. A
  *                             (method not given by the paper: block medians,
  *                             linear interpolation, normalised so that noise
- *                             powers follow the chi^2 law of Sec. 2.1)
+ *                             powers follow the chi^2 law of Sec. 2.1), per
+ *                             template or once per series
  *   O8 harmonic sum ......... Sec. 2.1 (S_L = sum_{n<=2^L} P_n), 16 harmonics
  *                             (Sec. 5.2)
  *   O9 thresholds ........... Sec. 2.1 (chi^2 with 2^(L+1) dof, false alarm)
@@ -56,6 +57,9 @@ typedef struct {
     double  threshold_sigma; /* one-sided Gaussian-equivalent threshold */
     double  fmin_hz;         /* lowest fundamental searched */
     double  fmax_hz;         /* highest fundamental searched; 0 = Nyquist */
+    int32_t series_whitening; /* 0: each template whitened by its own block
+                                 medians; 1: levels taken once from the
+                                 series' own spectrum (tbo_series_levels) */
 } tbo_config;
 
 typedef struct {
@@ -97,6 +101,12 @@ void tbo_power(const double* re, const double* im, int64_t nbins, double* p);
 /* O7: nbins = n/2 + 1.  med receives the block medians (ceil((nbins-1)/W)
  * values; may be NULL), phat the whitened spectrum. */
 void tbo_whiten(const double* p, int64_t nbins, int64_t w, double* med, double* phat);
+
+/* O7 once per series: block medians (ceil((nbins-1)/W) values, may be NULL)
+ * and the interpolated level m(k), k = 0..n/2 (lev[0] = 0), of the spectrum
+ * of x0 itself.  A template searched with cfg->series_whitening = 1 has
+ * P^_k = P_k ln2 / m(k).  Returns 0, or -1 on allocation failure. */
+int tbo_series_levels(const float* x0, const tbo_config* cfg, double* med, double* lev);
 
 /* O8: all folds 1..harm_max.  s has (log2(harm_max)+1) * nbins doubles,
  * fold l at s + l*nbins. */

@@ -9,6 +9,7 @@ import pytest
 import oracle
 from tests import test_oracle_end_to_end as E2E
 from tests import test_oracle_pins as PINS
+from tests import test_oracle_series_whitening as SW
 
 MUTANTS = {
     "kepler_step_sign": ("E -= step;", "E += step;"),
@@ -34,6 +35,11 @@ MUTANTS = {
     "tail_missing_term": ("for (int32_t k = 0; k < h; ++k) acc +=", "for (int32_t k = 0; k + 1 < h; ++k) acc +="),
     "gauss_tail_two_sided": ("return log(0.5 * erfc(z / sqrt(2.0)));", "return log(erfc(z / sqrt(2.0)));"),
     "fmin_not_scaled_by_fold": ("int64_t klo = h * J->kmin;", "int64_t klo = J->kmin;"),
+    "series_mode_ignored": ("if (lev) whiten_apply(w->p, nb, lev, w->phat);",
+                            "if (0) whiten_apply(w->p, nb, lev, w->phat);"),
+    "series_levels_window": ("whiten_levels(p, nb, cfg->whiten_window, med, lev);",
+                             "whiten_levels(p, nb, cfg->whiten_window + 1, med, lev);"),
+    "series_search_drops_levels": ("        J.lev = lev;\n", ""),
     "fold_pick_index": ("for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * hp)];",
                         "for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * h)];"),
 }
@@ -57,6 +63,11 @@ def _pins():
               E2E.test_injected_binary_peaks_at_true_template_and_frequency]:
         out.append(lambda f=f: f(None))
     out.append(lambda: PINS.test_fft_against_library(None, 14))
+    for f in [SW.test_series_levels_of_an_impulse_are_flat, SW.test_series_levels_of_a_silent_series_are_zero,
+              SW.test_series_medians_against_library_spectrum, SW.test_zero_orbit_matches_per_template_whitening,
+              SW.test_levels_do_not_depend_on_the_template,
+              SW.test_series_search_thresholds_the_series_whitened_sums]:
+        out.append(lambda f=f: f(None))
     return out
 
 
