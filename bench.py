@@ -72,16 +72,17 @@ def describe(w, name):
             "whiten_window": 4096}
 
 
-def kernel_bytes(n: int, templates_per_launch: float, tile: int = 8192):
+def kernel_bytes(n: int, templates_per_launch: float, tile: int = 8192, series_whitening: bool = False):
     """Algorithmic HBM bytes per launch of each kernel class, for series length n:
     the delay polynomials write 48 B per 16 tile points; pass 1 writes the
     4n-byte exchange per template and reads the 4n-byte series once per launch;
-    pass 2 reads 4n and writes 2n; the medians read the 2n-byte spectrum, the
-    whitening reads and rewrites it, the harmonic sum reads it once (first
+    pass 2 reads 4n and writes 2n (and, for a series whitened once, reads its
+    2n-byte factors once per launch); the medians read the 2n-byte spectrum,
+    the whitening reads and rewrites it, the harmonic sum reads it once (first
     touch)."""
     b = templates_per_launch
-    return [48.0 * min(tile, n // 2) / 16 * b, 4.0 * n * b + 4.0 * n, 6.0 * n * b, 2.0 * n * b, 4.0 * n * b,
-            2.0 * n * b]
+    return [48.0 * min(tile, n // 2) / 16 * b, 4.0 * n * b + 4.0 * n,
+            6.0 * n * b + (2.0 * n if series_whitening else 0.0), 2.0 * n * b, 4.0 * n * b, 2.0 * n * b]
 
 
 def traffic_record(kernel: str, workload_name: str):
@@ -100,14 +101,14 @@ def traffic_record(kernel: str, workload_name: str):
     return rec
 
 
-def cpu_baseline(w, seconds_hint: float):
+def cpu_baseline(w, seconds_hint: float, series_whitening: bool = False):
     import oracle
 
     oracle.build()
     threads = max(1, min(os.cpu_count() or 1, 16))
     x = w.series[0]
     n = x.size
-    cfg = oracle.config(n, w.tsamp)
+    cfg = oracle.config(n, w.tsamp, series_whitening=series_whitening)
     x0 = oracle.mean_subtract(x)
     t0 = time.perf_counter()
     oracle.search(x0, cfg, w.templates[:1], nthreads=1)
@@ -123,14 +124,14 @@ def cpu_baseline(w, seconds_hint: float):
             "single_thread_templates_per_s": 1.0 / one}
 
 
-def kernel_report(plan, n_avg: float, workload_name: str, tile: int):
+def kernel_report(plan, n_avg: float, workload_name: str, tile: int, series_whitening: bool = False):
     ms, launches, tmpl = plan.profile_read()
     plan.profile(False)
     per = []
     for k in range(len(KERNELS)):
         L = max(1, int(launches[k]))
         avg_ms = ms[k] / L
-        byt = kernel_bytes(int(n_avg), tmpl / L, tile)[k]
+        byt = kernel_bytes(int(n_avg), tmpl / L, tile, series_whitening)[k]
         per.append({"kernel": KERNEL_SHORT[k], "desc": KERNELS[k], "launches": int(launches[k]), "avg_ms": avg_ms,
                     "total_ms": float(ms[k]), "bytes_per_launch": byt,
                     "gbs": byt / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None})
@@ -184,13 +185,17 @@ def run_bank(args, tb, torch):
     conf = describe(w, args.workload)
     conf["tile_points"] = args.tile or default_tile(max(int(x.size) for x in w.series))
     conf["requests_per_series"] = max(1, args.split)
+    if args.series_whitening:
+        conf["whitening"] = "once per series (levels from the series' own spectrum)"
+    load_flags = tb.TB_SERIES_WHITENING if args.series_whitening else tb.TB_MEM_HOST
+    profile_name = args.workload + ("_series_whitening" if args.series_whitening else "")
     # one series: waves of one stream keep the device busy (lanes add no throughput there);
     # several series: one request per series, spread over four lanes
     lanes = args.lanes or (4 if len(w.series) > 1 else 1)
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
                    threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18,
                    tile_points=args.tile)
-    sids = [plan.load_series(s, w.tsamp) for s in w.series]
+    sids = [plan.load_series(s, w.tsamp, flags=load_flags) for s in w.series]
     ntemp = len(w.templates)
     nitems = ntemp * len(sids)
 
@@ -223,15 +228,18 @@ def run_bank(args, tb, torch):
     log("timed %d steps: %.1f ms/step, %.0f templates/s, %d candidates/step" % (args.steps, ms_step, value,
                                                                                 ncand // max(1, args.steps)))
     samples_total = float(sum(s.size for s in w.series))
-    out = {"metric": METRIC if args.workload == "c2" else "templates/s (%s)" % args.workload, "value": value,
+    metric = METRIC if args.workload == "c2" else "templates/s (%s)" % args.workload
+    if args.series_whitening:
+        metric += " [whitened once per series]"
+    out = {"metric": metric, "value": value,
            "unit": "templates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": conf, "candidates_per_step": ncand // max(1, args.steps),
            "algorithmic_gbs": 12.0 * samples_total * ntemp * args.steps / dt / 1e9}
     out["algorithmic_hbm_frac"] = out["algorithmic_gbs"] / PEAK_HBM_GBS
     if not args.no_profile:
-        out["kernels"], out["roofline"] = kernel_report(plan, samples_total / len(w.series), args.workload,
-                                                     conf["tile_points"])
+        out["kernels"], out["roofline"] = kernel_report(plan, samples_total / len(w.series), profile_name,
+                                                     conf["tile_points"], args.series_whitening)
         out["stream_copy_gbs"] = stream_copy_gbs(plan, tb)
     plan.close()
     if args.workload == "c4" and not args.no_plain:
@@ -243,7 +251,7 @@ def run_bank(args, tb, torch):
         out["batched_vs_plain"] = rates["batched"] / rates["plain"]
     if not args.no_cpu_baseline and args.workload in ("c1", "c2", "c3"):
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.series_whitening)
     return out
 
 
@@ -315,6 +323,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--split", type=int, default=1, help="requests the bank is cut into per series (spread over lanes)")
     ap.add_argument("--tile", type=int, default=0, help="FFT points per workgroup, 8192 or 16384 (0 = library default)")
+    ap.add_argument("--series-whitening", action="store_true",
+                    help="whiten once per series (levels from its own spectrum) instead of per template")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")

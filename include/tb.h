@@ -48,7 +48,9 @@ typedef enum {
     TB_ERR_UNKNOWN_ID = -7   /* no such series or request */
 } tb_status;
 
-enum { TB_MEM_HOST = 0, TB_MEM_DEVICE = 1 };
+/* tb_load_series flags: where data lives (one of the two), optionally ORed
+ * with TB_SERIES_WHITENING. */
+enum { TB_MEM_HOST = 0, TB_MEM_DEVICE = 1, TB_SERIES_WHITENING = 2 };
 
 typedef struct {
     uint32_t max_log2n;        /* largest series accepted, log2 samples, 10..24 */
@@ -109,7 +111,16 @@ tb_status tb_destroy(tb_plan_t plan);
 /* Copies a dedispersed series S_i, i = 0..n-1 at times i*tsamp (App. A.1),
  * into plan memory (from host, or device-to-device on the plan stream for
  * TB_MEM_DEVICE) and removes its mean in double precision.  Returns the new
- * id in *series_id.  TB_ERR_BUDGET if it does not fit the HBM budget. */
+ * id in *series_id.  TB_ERR_BUDGET if it does not fit the HBM budget.
+ *
+ * With TB_SERIES_WHITENING the Fourier de-reddening (App. A, Sec. 5.2) is done
+ * once for the series instead of once per template: the block medians of the
+ * power spectrum of the series as loaded (no demodulation) give the level
+ * m(k), and every template searched on the series has P^_k = P_k ln2 / m(k)
+ * (0 where m(k) <= 0; P^_0 = 0).  The per-template block-median and whitening
+ * kernels then do not run.  The series holds 4 (n/2 + 1) more bytes, and
+ * loading it allocates the search workspace of its length if the plan does not
+ * hold it yet. */
 tb_status tb_load_series(tb_plan_t plan, const float* data, uint64_t n, double tsamp_s,
                          uint32_t flags, int32_t* series_id);
 
@@ -157,7 +168,8 @@ const char* tb_strerror(tb_status status);
  * (same kernels as tb_search_templates).  Host buffers, any may be NULL:
  *   src    int32[n]      input index read for output sample j (Algorithm 1)
  *   power  float[n/2+1]  P_k = |X_k|^2 of the demodulated series
- *   medians float[ceil((n/2)/W)]  whitening block medians
+ *   medians float[ceil((n/2)/W)]  whitening block medians (of the series itself
+ *                        for a series loaded with TB_SERIES_WHITENING)
  *   sums   float[(log2(harm_max)+1) * (n/2+1)]  S_h[k] per fold
  * Candidates of this template are not kept. */
 tb_status tb_inspect_template(tb_plan_t plan, int32_t series_id, const tb_template* t,

@@ -27,6 +27,7 @@ TB_ERR_NOT_READY = -6
 TB_ERR_UNKNOWN_ID = -7
 TB_MEM_HOST = 0
 TB_MEM_DEVICE = 1
+TB_SERIES_WHITENING = 2  # OR into the load flags: whiten once from the series' own spectrum
 
 
 class TbConfig(C.Structure):
@@ -172,9 +173,10 @@ def tb_destroy(plan: int) -> None:
 
 
 def tb_load_series(plan: int, data, tsamp: float, n: int | None = None, flags: int = TB_MEM_HOST) -> int:
-    """data: float32 numpy array (TB_MEM_HOST) or a device address (TB_MEM_DEVICE, n required)."""
+    """data: float32 numpy array (TB_MEM_HOST) or a device address (TB_MEM_DEVICE, n required);
+    flags may also carry TB_SERIES_WHITENING."""
     sid = C.c_int32(-1)
-    if flags == TB_MEM_HOST:
+    if (flags & TB_MEM_DEVICE) == TB_MEM_HOST:
         data = np.ascontiguousarray(data, dtype=np.float32)
         n = data.size
     _check(_L.tb_load_series(C.c_void_p(plan), _ptr(data), int(n), float(tsamp), int(flags), C.byref(sid)),
@@ -336,7 +338,7 @@ class Plan:
 
     def load_series(self, data, tsamp, n=None, flags=TB_MEM_HOST) -> int:
         sid = tb_load_series(self.handle, data, tsamp, n=n, flags=flags)
-        self.series_n[sid] = int(n if n is not None else np.asarray(data).size)
+        self.series_n[sid] = int(n if (flags & TB_MEM_DEVICE) else np.asarray(data).size)
         return sid
 
     def unload_series(self, sid):

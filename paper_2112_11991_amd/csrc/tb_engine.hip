@@ -109,7 +109,9 @@ struct SeriesRec {
     int64_t n = 0;
     double tsamp = 0;
     float* d = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;     // everything the series holds
+    float* fac = nullptr; // whitened once: factors ln2 / m(k), M + 1 floats; nullptr = per template
+    float* med = nullptr; // and the series' block medians (same allocation)
 };
 
 struct GeoRec {
@@ -459,7 +461,8 @@ tb_status enqueue(tb_plan_t p, const Crew& crew, const SeriesRec& sr, Geometry* 
             marks = &p->prof_events.back();
             p->prof_templates += (uint64_t)nslots;
         }
-        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, pp, ring, counter, ins, stream, marks) !=
+        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, sr.fac, pp, ring, counter, ins, stream,
+                        marks) !=
             hipSuccess)
             return TB_ERR_DEVICE;
         w0 += (uint32_t)nslots;
@@ -658,45 +661,64 @@ tb_status tb_destroy(tb_plan_t p)
 
 tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsamp, uint32_t flags, int32_t* id)
 {
+    const uint32_t mem = flags & ~(uint32_t)TB_SERIES_WHITENING;
+    const bool once = (flags & TB_SERIES_WHITENING) != 0;
     if (!p || !data || !id || !pow2(n) || n < 1024 || n > (1ull << p->cfg.max_log2n) || !(tsamp > 0.0) ||
-        !std::isfinite(tsamp) || (flags != TB_MEM_HOST && flags != TB_MEM_DEVICE))
+        !std::isfinite(tsamp) || (mem != TB_MEM_HOST && mem != TB_MEM_DEVICE))
         return TB_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(p->mu);
     TB_TRY(hipSetDevice(p->cfg.device));
     if (p->next_series >= (1 << 24)) return TB_ERR_INVALID_ARG;
+    Geometry* g = nullptr;
+    tb_status st = get_geometry(p, ilog2(n), &g);
+    if (st) return st;
+    Slots* ws = nullptr;
+    if (once && (st = get_slots(p, 0, *g, &ws))) return st;
     SeriesRec r;
     r.n = (int64_t)n;
     r.tsamp = tsamp;
-    r.bytes = sizeof(float) * (n + SERIES_PAD);
-    tb_status st = reserve(p, r.bytes);
-    if (st) return st;
-    if (hipMalloc(&r.d, r.bytes) != hipSuccess) {
+    const size_t series_bytes = sizeof(float) * (n + SERIES_PAD);
+    const size_t fac_floats = ((size_t)g->M + 1 + 63) & ~(size_t)63;
+    r.bytes = series_bytes + (once ? sizeof(float) * (fac_floats + (size_t)g->nblk) : 0);
+    if ((st = reserve(p, r.bytes))) return st;
+    // one allocation: series (and padding), then factors and medians
+    char* mem_d = nullptr;
+    if (hipMalloc(&mem_d, r.bytes) != hipSuccess) {
         p->held -= r.bytes;
         return TB_ERR_OOM;
     }
-    Geometry* g = nullptr;
-    tb_status gst = get_geometry(p, ilog2(n), &g);
-    if (gst) {
-        hipFree(r.d);
-        p->held -= r.bytes;
-        return gst;
+    r.d = (float*)mem_d;
+    if (once) {
+        r.fac = (float*)(mem_d + series_bytes);
+        r.med = r.fac + fac_floats;
     }
-    // staging: [0, n) raw copy (host input), [n, 2n) mean-removed natural order
+    // staging: [0, n) raw copy (host input), [n, 2n) mean-removed natural
+    // order, then a template without orbit for the series levels
     float* staging = nullptr;
-    if (hipMalloc(&staging, 2 * sizeof(float) * n) != hipSuccess) {
+    const size_t tmpl_off = ((2 * sizeof(float) * n) + 255) & ~(size_t)255;
+    if (hipMalloc(&staging, tmpl_off + 256) != hipSuccess) {
         hipFree(r.d);
         p->held -= r.bytes;
         return TB_ERR_OOM;
     }
     const float* src = data;
     hipError_t e = hipSuccess;
-    if (flags == TB_MEM_HOST) {
+    if (mem == TB_MEM_HOST) {
         e = hipMemcpyAsync(staging, data, sizeof(float) * n, hipMemcpyHostToDevice, p->stream);
         src = staging;
     }
     if (e == hipSuccess) e = launch_mean_subtract(src, staging + n, r.n, p->d_partial, p->stream);
     if (e == hipSuccess) e = launch_tile_series(*g, staging + n, r.d, p->stream);
     if (e == hipSuccess) e = hipMemsetAsync(r.d + n, 0, sizeof(float) * SERIES_PAD, p->stream);
+    if (e == hipSuccess && once) {
+        // tau = 0: the demodulation reads every sample where it is
+        static const tb_template still = {1.0, 0.0, 0.0, 0.0, 0.0};
+        tb_template* d_t = (tb_template*)((char*)staging + tmpl_off);
+        TmplDev* d_tm = (TmplDev*)((char*)staging + tmpl_off + 128);
+        e = hipMemcpyAsync(d_t, &still, sizeof(still), hipMemcpyHostToDevice, p->stream);
+        if (e == hipSuccess) e = launch_template_prep(d_t, 1, d_tm, p->stream);
+        if (e == hipSuccess) e = launch_series_levels(*g, r.d, tsamp, d_tm, *ws, r.med, r.fac, p->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     hipFree(staging);
     if (e != hipSuccess) {
@@ -1056,12 +1078,23 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     ins.src = (int32_t*)(d + 512 + sizeof(uint4) * 16);
     ins.sums = (float*)((char*)ins.src + sizeof(int32_t) * (size_t)sr.n);
     ins.power = ins.sums + (size_t)nfold * nb;
+    float* const d_power = ins.power;
     PeakParams pp = peak_params(p, sr.n, sr.tsamp, (uint32_t)sid, 0, 0);
     st = TB_OK;
     if (launch_fill_u32(counter, 0u, 1, p->stream) != hipSuccess ||
         hipMemcpyAsync(d_t, ht, sizeof(tb_template), hipMemcpyHostToDevice, p->stream) != hipSuccess ||
         launch_template_prep(d_t, 1, d_tm, p->stream) != hipSuccess)
         st = TB_ERR_DEVICE;
+    if (!st && sr.fac && power) {
+        // a series whitened once: pass 2 of the search stores whitened power,
+        // so the raw power comes from a pass without the factors
+        Inspect raw;
+        raw.power = ins.power;
+        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, 0, 1, *ws, nullptr, pp, ring, counter, raw, p->stream) !=
+            hipSuccess)
+            st = TB_ERR_DEVICE;
+        ins.power = nullptr;
+    }
     Crew crew;
     crew.streams.push_back(p->stream);
     crew.slots.push_back(ws);
@@ -1069,10 +1102,12 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     if (!st && hipStreamSynchronize(p->stream) != hipSuccess) st = TB_ERR_DEVICE;
     if (!st && src && hipMemcpy(src, ins.src, sizeof(int32_t) * (size_t)sr.n, hipMemcpyDeviceToHost) != hipSuccess)
         st = TB_ERR_DEVICE;
-    if (!st && power && hipMemcpy(power, ins.power, sizeof(float) * nb, hipMemcpyDeviceToHost) != hipSuccess)
+    if (!st && power &&
+        hipMemcpy(power, d_power, sizeof(float) * nb, hipMemcpyDeviceToHost) != hipSuccess)
         st = TB_ERR_DEVICE;
     if (!st && medians &&
-        hipMemcpy(medians, ws->med, sizeof(float) * (size_t)g->nblk, hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(medians, sr.fac ? sr.med : ws->med, sizeof(float) * (size_t)g->nblk, hipMemcpyDeviceToHost) !=
+            hipSuccess)
         st = TB_ERR_DEVICE;
     if (!st && sums && hipMemcpy(sums, ins.sums, sizeof(float) * nfold * nb, hipMemcpyDeviceToHost) != hipSuccess)
         st = TB_ERR_DEVICE;

@@ -608,12 +608,18 @@ __device__ __forceinline__ float power_of(float2 z, float2 zm, float2 w)
 // loads slot q = t % D2 of blocks w = t / D2 + RK i, so all of its addresses
 // are a per-thread base plus compile-time steps; other geometries take the
 // general index arithmetic.  Thread t emits bins k1 = t / D2 + RK i of slot q.
+//
+// With fac (a series whitened once, bins 0..M like one power row), every bin
+// is stored as |X_k|^2 fac_k, the whitened power; without it fac_k = 1 and
+// the raw power is stored.  The factors are loaded before the transform so
+// that their latency hides behind it.
 template <int R, int D2>
 __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__ Y, size_t y_stride, int S, int lgS,
                                                       int lgC1, float* __restrict__ P, size_t p_stride, int64_t M,
                                                       const float2* __restrict__ twst,
                                                       const float2* __restrict__ tw2M_lo,
-                                                      const float2* __restrict__ tw2M_hi)
+                                                      const float2* __restrict__ tw2M_hi,
+                                                      const float* __restrict__ fac)
 {
     constexpr int T = D2 * R / 16, LSP = R + R / 16 + 1, D = D2 / 2, RK = R / 16, LD2 = Log2<D2>::value;
     // R > 16 with one pass-1 column per workgroup (the plan's geometries)
@@ -655,6 +661,17 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
 #pragma unroll
         for (int i = 0; i < 16; ++i) lds[laddr[i]] = v[i];
     }
+    const uint32_t soff0 = ((uint32_t)col + ((uint32_t)k1t << lgS)) << 2;
+    const uint32_t sstep = (uint32_t)RK << (lgS + 2);
+    float fv[16];
+    if (fac) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            fv[i] = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(fac) + (soff0 + sstep * (uint32_t)i));
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) fv[i] = 1.0f;
+    }
     __syncthreads();
     fft_tile<R, D2>(lds, twst);
 
@@ -664,10 +681,8 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
     const bool self = q < D && a == 0;  // column 0: Z_{M-k} at k1' = (R - k1) mod R
     float2 w = twiddle2(tw2M_lo, tw2M_hi, (uint32_t)col + (uint32_t)S * (uint32_t)k1t);
     const float2 z = make_float2(0.98078528040323044913f, -0.19509032201612826785f);
-    const uint32_t soff0 = ((uint32_t)col + ((uint32_t)k1t << lgS)) << 2;
-    const uint32_t sstep = (uint32_t)RK << (lgS + 2);
     auto store = [&](int i, float v) {
-        *reinterpret_cast<float*>(reinterpret_cast<char*>(Ps) + (soff0 + sstep * (uint32_t)i)) = v;
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(Ps) + (soff0 + sstep * (uint32_t)i)) = v * fv[i];
     };
     if (self && k1t == 0) {
         // bins k1 = RK i of column 0; bin 0 pairs with itself, and the
@@ -682,7 +697,7 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
             w = cmul(w, z);
             if (i == 0) {
                 const float sm = zo.x - zo.y;
-                Ps[M] = sm * sm;
+                Ps[M] = sm * sm * (fac ? fac[M] : 1.0f);
             }
         }
     } else {
@@ -793,44 +808,75 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
 
 // Whitening: P^_k = P_k ln2 / m(k), m the straight line between neighbouring
 // block-median centres c_b = start_b + (n_b - 1)/2, held constant before the
-// first and after the last centre; P^_0 = 0.  One workgroup per block, in
-// place.  Centres are kept doubled so that they stay integers (below 2^24, so
-// exact in FP32); the line is evaluated as m_left + slope (2q - 2c_left).
+// first and after the last centre; P^_0 = 0.  One workgroup per block.
+// Centres are kept doubled so that they stay integers (below 2^24, so exact
+// in FP32); the line is evaluated as m_left + slope (2q - 2c_left).
+struct WhitenLine {
+    int start, cnt;
+    float s_l, s_r, base_l, ml0, fc, m_here;
+    __device__ __forceinline__ float level(int q) const
+    {
+        const float x = (float)(2 * q);
+        return x < fc ? fmaf(s_l, x - base_l, ml0) : fmaf(s_r, x - fc, m_here);
+    }
+};
+
+__device__ __forceinline__ WhitenLine whiten_line(const float* __restrict__ md, int b, int Mi, int W, int nblk)
+{
+    auto two_c = [&](int bb) -> int {
+        const int n_b = (bb == nblk - 1) ? (Mi - bb * W) : W;
+        return 2 * bb * W + n_b + 1;
+    };
+    WhitenLine L;
+    L.start = 1 + b * W;
+    L.cnt = (Mi - b * W) < W ? (Mi - b * W) : W;
+    const int c_here = two_c(b);
+    L.m_here = md[b];
+    // left segment [c_{b-1}, c_b), right [c_b, c_{b+1}); flat outside the first/last centre
+    const bool has_l = b > 0, has_r = b + 1 < nblk;
+    const int c_l = has_l ? two_c(b - 1) : c_here, c_r = has_r ? two_c(b + 1) : c_here;
+    const float m_l = has_l ? md[b - 1] : L.m_here, m_r = has_r ? md[b + 1] : L.m_here;
+    L.s_l = has_l ? (L.m_here - m_l) / (float)(c_here - c_l) : 0.0f;
+    L.s_r = has_r ? (m_r - L.m_here) / (float)(c_r - c_here) : 0.0f;
+    L.base_l = has_l ? (float)c_l : (float)c_here;
+    L.ml0 = has_l ? m_l : L.m_here;
+    L.fc = (float)c_here;
+    return L;
+}
+
+constexpr float LN2F = 0.69314718055994530942f;
+
+// Per template, in place.
 __global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_stride, int64_t M, int W, int nblk,
                                                const float* __restrict__ med, size_t med_stride)
 {
     const int b = blockIdx.x;
     float* Ps = P + blockIdx.y * p_stride;
-    const float* md = med + blockIdx.y * med_stride;
-    const int Mi = (int)M;
-    const int start = 1 + b * W;
-    const int cnt = (Mi - b * W) < W ? (Mi - b * W) : W;
-    auto two_c = [&](int bb) -> int {
-        const int n_b = (bb == nblk - 1) ? (Mi - bb * W) : W;
-        return 2 * bb * W + n_b + 1;
-    };
-    const int c_here = two_c(b);
-    const float m_here = md[b];
-    // left segment [c_{b-1}, c_b), right [c_b, c_{b+1}); flat outside the first/last centre
-    const bool has_l = b > 0, has_r = b + 1 < nblk;
-    const int c_l = has_l ? two_c(b - 1) : c_here, c_r = has_r ? two_c(b + 1) : c_here;
-    const float m_l = has_l ? md[b - 1] : m_here, m_r = has_r ? md[b + 1] : m_here;
-    const float s_l = has_l ? (m_here - m_l) / (float)(c_here - c_l) : 0.0f;
-    const float s_r = has_r ? (m_r - m_here) / (float)(c_r - c_here) : 0.0f;
-    const float base_l = has_l ? (float)c_l : (float)c_here;
-    const float ml0 = has_l ? m_l : m_here;
-    const float fc = (float)c_here;
-    constexpr float LN2 = 0.69314718055994530942f;
+    const WhitenLine L = whiten_line(med + blockIdx.y * med_stride, b, (int)M, W, nblk);
 #pragma unroll 4
-    for (int i = threadIdx.x; i < cnt; i += NT) {
-        const int q = start + i;
-        const float x = (float)(2 * q);
-        const bool left = x < fc;
-        const float level = left ? fmaf(s_l, x - base_l, ml0) : fmaf(s_r, x - fc, m_here);
+    for (int i = threadIdx.x; i < L.cnt; i += NT) {
+        const int q = L.start + i;
+        const float level = L.level(q);
         const float p = Ps[q];
-        Ps[q] = level > 0.0f ? p * (LN2 * __builtin_amdgcn_rcpf(level)) : 0.0f;
+        Ps[q] = level > 0.0f ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
     }
     if (b == 0 && threadIdx.x == 0) Ps[0] = 0.0f;
+}
+
+// Once per series: the factor ln2 / m(k) (0 where m(k) <= 0, and at k = 0)
+// that pass 2 applies to every template's power, the same float k_whiten
+// multiplies by.
+__global__ __launch_bounds__(NT) void k_series_factor(const float* __restrict__ med, int64_t M, int W, int nblk,
+                                                      float* __restrict__ fac)
+{
+    const int b = blockIdx.x;
+    const WhitenLine L = whiten_line(med, b, (int)M, W, nblk);
+    for (int i = threadIdx.x; i < L.cnt; i += NT) {
+        const int q = L.start + i;
+        const float level = L.level(q);
+        fac[q] = level > 0.0f ? LN2F * __builtin_amdgcn_rcpf(level) : 0.0f;
+    }
+    if (b == 0 && threadIdx.x == 0) fac[0] = 0.0f;
 }
 
 // ------------------------------------------------------------------------
@@ -970,12 +1016,12 @@ hipError_t fft1_launch(const Geometry& g, const float* x, double tsamp, const Tm
 }
 
 template <int R, int D2>
-hipError_t fft2_launch(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
+hipError_t fft2_launch(const Geometry& g, int nslots, const Slots& ws, const float* fac, hipStream_t s)
 {
     dim3 grid(g.S / D2, nslots);
     hipLaunchKernelGGL((k_fft2<R, D2>), grid, dim3(D2 * R / 16), 0, s, ws.Y, ws.y_stride, g.S, ilog2i(g.S),
                        ilog2i(g.C1), ws.P,
-                       ws.p_stride, g.M, g.twst, g.tw2M_lo, g.tw2M_hi);
+                       ws.p_stride, g.M, g.twst, g.tw2M_lo, g.tw2M_hi, fac);
     return hipGetLastError();
 }
 
@@ -998,10 +1044,11 @@ hipError_t fft1_dispatch(const Geometry& g, const float* x, double tsamp, const 
     return e;
 }
 template <class... K>
-hipError_t fft2_dispatch(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
+hipError_t fft2_dispatch(const Geometry& g, int nslots, const Slots& ws, const float* fac, hipStream_t s)
 {
     hipError_t e = hipErrorInvalidValue;
-    (void)((g.R == K::a && g.D2 == K::b ? (e = fft2_launch<K::a, K::b>(g, nslots, ws, s), true) : false) || ...);
+    (void)((g.R == K::a && g.D2 == K::b ? (e = fft2_launch<K::a, K::b>(g, nslots, ws, fac, s), true) : false) ||
+           ...);
     return e;
 }
 
@@ -1014,12 +1061,12 @@ hipError_t launch_fft1(const Geometry& g, const float* x, double tsamp, const Tm
                                                                                          ws, src_out, s);
 }
 
-hipError_t launch_fft2(const Geometry& g, int nslots, const Slots& ws, hipStream_t s)
+hipError_t launch_fft2(const Geometry& g, int nslots, const Slots& ws, const float* fac, hipStream_t s)
 {
     return fft2_dispatch<Shape<16, 32>, Shape<16, 64>, Shape<16, 128>, Shape<16, 256>, Shape<16, 512>,
                          Shape<16, 1024>, Shape<32, 512>, Shape<64, 256>, Shape<128, 128>, Shape<256, 64>,
                          Shape<512, 32>, Shape<32, 256>, Shape<64, 128>, Shape<128, 64>, Shape<256, 32>,
-                         Shape<512, 16>, Shape<1024, 8>>(g, nslots, ws, s);
+                         Shape<512, 16>, Shape<1024, 8>>(g, nslots, ws, fac, s);
 }
 
 }  // namespace
@@ -1067,21 +1114,26 @@ hipError_t launch_copy(float4* dst, const float4* src, size_t count, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
-                       int nslots, const Slots& ws, const PeakParams& pp, uint4* ring, uint32_t* counter,
-                       const Inspect& ins, hipStream_t s, Marks* marks)
+namespace {
+
+// Records an event of kernel class cls on s into marks (none without marks).
+hipError_t mark(Marks* marks, int cls, hipStream_t s)
+{
+    if (!marks) return hipSuccess;
+    hipEvent_t ev = nullptr;
+    hipError_t r = hipEventCreate(&ev);
+    if (r != hipSuccess) return r;
+    marks->emplace_back(cls, ev);
+    return hipEventRecord(ev, s);
+}
+
+// Delay polynomials, then passes 1 and 2 in groups of ws.BY templates: the
+// power (whitened by fac when given) of nslots templates in ws.P.
+hipError_t launch_power(const Geometry& g, const float* x, double tsamp, const TmplDev* tmw, int nslots,
+                        const Slots& ws, const float* fac, int32_t* src_out, hipStream_t s, Marks* marks)
 {
     hipError_t e;
-    auto mark = [&](int cls) -> hipError_t {
-        if (!marks) return hipSuccess;
-        hipEvent_t ev = nullptr;
-        hipError_t r = hipEventCreate(&ev);
-        if (r != hipSuccess) return r;
-        marks->emplace_back(cls, ev);
-        return hipEventRecord(ev, s);
-    };
-    const TmplDev* tmw = tm + tmpl_base;
-    if ((e = mark(K_POLY)) != hipSuccess) return e;
+    if ((e = mark(marks, K_POLY, s)) != hipSuccess) return e;
     const int npts = (int)std::min<int64_t>(g.TE, g.M), nchunk = npts / 8;
     hipLaunchKernelGGL(k_chunk_polys, dim3((nchunk + NT - 1) / NT, nslots), dim3(NT), 0, s, tmw, tsamp, g.R, g.C1,
                        npts, ws.poly, ws.poly_stride, ws.pok);
@@ -1092,29 +1144,58 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
         grp.poly = ws.poly + (size_t)q0 * ws.poly_stride;
         grp.pok = ws.pok + q0;
         grp.P = ws.P + (size_t)q0 * ws.p_stride;
-        int32_t* src = q0 == 0 ? ins.src : nullptr;
-        if ((e = mark(K_PASS1)) != hipSuccess) return e;
-        if ((e = launch_fft1(g, x, tsamp, tmw + q0, nq, grp, src, s)) != hipSuccess) return e;
-        if ((e = mark(K_PASS2)) != hipSuccess) return e;
-        if ((e = launch_fft2(g, nq, grp, s)) != hipSuccess) return e;
+        if ((e = mark(marks, K_PASS1, s)) != hipSuccess) return e;
+        if ((e = launch_fft1(g, x, tsamp, tmw + q0, nq, grp, q0 == 0 ? src_out : nullptr, s)) != hipSuccess)
+            return e;
+        if ((e = mark(marks, K_PASS2, s)) != hipSuccess) return e;
+        if ((e = launch_fft2(g, nq, grp, fac, s)) != hipSuccess) return e;
     }
+    return hipSuccess;
+}
+
+hipError_t launch_median(const Geometry& g, int nslots, const Slots& ws, float* med, size_t med_stride,
+                         hipStream_t s)
+{
+    if (g.W <= 16 * NT)
+        hipLaunchKernelGGL((k_median<16>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, med,
+                           med_stride);
+    else
+        hipLaunchKernelGGL((k_median<32>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, med,
+                           med_stride);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_series_levels(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, const Slots& ws,
+                                float* med, float* fac, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = launch_power(g, x, tsamp, tm, 1, ws, nullptr, nullptr, s, nullptr)) != hipSuccess) return e;
+    if ((e = launch_median(g, 1, ws, med, 0, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_series_factor, dim3(g.nblk), dim3(NT), 0, s, med, g.M, g.W, g.nblk, fac);
+    return hipGetLastError();
+}
+
+hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
+                       int nslots, const Slots& ws, const float* fac, const PeakParams& pp, uint4* ring,
+                       uint32_t* counter, const Inspect& ins, hipStream_t s, Marks* marks)
+{
+    hipError_t e;
+    if ((e = launch_power(g, x, tsamp, tm + tmpl_base, nslots, ws, fac, ins.src, s, marks)) != hipSuccess) return e;
     if (ins.power &&
         (e = hipMemcpyAsync(ins.power, ws.P, sizeof(float) * (size_t)(g.M + 1), hipMemcpyDeviceToDevice, s)) !=
             hipSuccess)
         return e;
-    if ((e = mark(K_MEDIAN)) != hipSuccess) return e;
-    if (g.W <= 16 * NT)
-        hipLaunchKernelGGL((k_median<16>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
+    if (!fac) {
+        if ((e = mark(marks, K_MEDIAN, s)) != hipSuccess) return e;
+        if ((e = launch_median(g, nslots, ws, ws.med, ws.med_stride, s)) != hipSuccess) return e;
+        if ((e = mark(marks, K_WHITEN, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk,
                            ws.med, ws.med_stride);
-    else
-        hipLaunchKernelGGL((k_median<32>), dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W,
-                           ws.med, ws.med_stride);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = mark(K_WHITEN)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk, ws.med,
-                       ws.med_stride);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = mark(K_HARMSUM)) != hipSuccess) return e;
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if ((e = mark(marks, K_HARMSUM, s)) != hipSuccess) return e;
     dim3 hg(g.hgrid, nslots);
     switch (pp.nfold) {
     case 1: hipLaunchKernelGGL((k_harmsum<1>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
@@ -1125,7 +1206,7 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
     default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return mark(-1);
+    return mark(marks, -1, s);
 }
 
 }  // namespace tb
