@@ -161,6 +161,9 @@ def _bind(L):
         C.c_void_p, C.c_int64, P(C.c_int64),
     ]
     L.tbo_search.restype = C.c_int
+    L.tbo_distill.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                              P(C.c_int64)]
+    L.tbo_distill.restype = C.c_int
     return L
 
 
@@ -335,3 +338,16 @@ def search(x0: np.ndarray, cfg: Config, templates, first_template_id: int = 0, s
         if ntot.value <= cap:
             return out[: ntot.value]
         cap = ntot.value
+
+
+def distill(cands: np.ndarray, max_ratio: int = 16, tol: int = 16, ppm: int = 0):
+    """Candidate grouping: (kept candidates in strength order, group sizes).
+    tol: sixteenths of a fundamental bin; ppm: parts per million of the target."""
+    c = np.ascontiguousarray(cands, dtype=CANDIDATE_DTYPE)
+    out = np.zeros(max(1, c.size), dtype=CANDIDATE_DTYPE)
+    grp = np.zeros(max(1, c.size), dtype=np.int64)
+    nk = C.c_int64(0)
+    if lib().tbo_distill(_ptr(c), c.size, int(max_ratio), int(tol), int(ppm), _ptr(out), _ptr(grp),
+                         C.byref(nk)) != 0:
+        raise ValueError("tbo_distill: bad arguments")
+    return out[: nk.value], grp[: nk.value]

@@ -577,3 +577,93 @@ int tbo_search(const float* x0, const tbo_config* cfg, const tbo_template* t,
     *n_total = tot;
     return J.failed ? -1 : 0;
 }
+
+/* ----------------------------------------------------------- O11 -------- */
+/* Candidate grouping (App. A: detections of the same signal are grouped and
+ * the strongest kept; the paper gives no algorithm, so this is a definition).
+ * Position of a candidate's fundamental in 1/16 fundamental bins:
+ * F = 16 k / h = k * 2^(4 - log2_harm), an integer.  Strength order: sigma
+ * descending, then series, template, fold, bin ascending.  A candidate b is
+ * related to a stronger one a when they share the series and, for some
+ * integers 1 <= p, q <= max_ratio, F_b lies within tol + ppm 1e-6 (p/q) F_a of
+ * (p/q) F_a; times 1e6 q, in integers:
+ *   1e6 |q F_b - p F_a| <= 1e6 q tol + ppm p F_a.
+ * Walking the strength order, a candidate nobody
+ * stronger has absorbed is kept and absorbs every weaker, not yet absorbed
+ * candidate related to it. */
+static int64_t cand_F(const tbo_candidate* c)
+{
+    return (int64_t)c->bin << (4 - c->log2_harm);
+}
+
+static int stronger(const tbo_candidate* a, const tbo_candidate* b)
+{
+    if (a->sigma != b->sigma) return a->sigma > b->sigma;
+    if (a->series_id != b->series_id) return a->series_id < b->series_id;
+    if (a->template_id != b->template_id) return a->template_id < b->template_id;
+    if (a->log2_harm != b->log2_harm) return a->log2_harm < b->log2_harm;
+    return a->bin < b->bin;
+}
+
+static const tbo_candidate* g_sort_base; /* qsort context (the oracle's grouping is not reentrant) */
+static int cmp_strength(const void* x, const void* y)
+{
+    const tbo_candidate* a = &g_sort_base[*(const int64_t*)x];
+    const tbo_candidate* b = &g_sort_base[*(const int64_t*)y];
+    if (stronger(a, b)) return -1;
+    if (stronger(b, a)) return 1;
+    return 0;
+}
+
+static int related(const tbo_candidate* a, const tbo_candidate* b, int32_t max_ratio, int64_t tol, int64_t ppm)
+{
+    if (a->series_id != b->series_id) return 0;
+    int64_t fa = cand_F(a), fb = cand_F(b);
+    for (int64_t p = 1; p <= max_ratio; ++p)
+        for (int64_t q = 1; q <= max_ratio; ++q) {
+            int64_t d = q * fb - p * fa;
+            if (d < 0) d = -d;
+            if (1000000 * d <= 1000000 * q * tol + ppm * p * fa) return 1;
+        }
+    return 0;
+}
+
+int tbo_distill(const tbo_candidate* in, int64_t n, int32_t max_ratio, int64_t tol, int64_t ppm,
+                tbo_candidate* out, int64_t* group, int64_t* n_kept)
+{
+    if (n < 0 || (n > 0 && (!in || !out)) || !n_kept || max_ratio < 1 || max_ratio > 64 || tol < 0 ||
+        tol > (1 << 20) || ppm < 0 || ppm > 1000000)
+        return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (in[i].log2_harm < 0 || in[i].log2_harm > 4) return -1;
+    int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    char* absorbed = (char*)calloc((size_t)(n ? n : 1), 1);
+    if (!order || !absorbed) {
+        free(order);
+        free(absorbed);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) order[i] = i;
+    g_sort_base = in;
+    qsort(order, (size_t)n, sizeof(int64_t), cmp_strength);
+    int64_t kept = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t a = order[i];
+        if (absorbed[a]) continue;
+        int64_t members = 1;
+        for (int64_t j = i + 1; j < n; ++j) {
+            int64_t b = order[j];
+            if (!absorbed[b] && related(&in[a], &in[b], max_ratio, tol, ppm)) {
+                absorbed[b] = 1;
+                ++members;
+            }
+        }
+        out[kept] = in[a];
+        if (group) group[kept] = members;
+        ++kept;
+    }
+    *n_kept = kept;
+    free(order);
+    free(absorbed);
+    return 0;
+}

@@ -29,6 +29,9 @@
  *                             (Sec. 5.2)
  *   O9 thresholds ........... Sec. 2.1 (chi^2 with 2^(L+1) dof, false alarm)
  *   O10 candidates .......... peak detection, App. A
+ *   O11 grouping ............ candidate reduction by grouping repeated
+ *                             detections, App. A (method not given by the
+ *                             paper: greedy harmonic grouping, see tbo.c)
  */
 #ifndef TBO_H
 #define TBO_H
@@ -132,6 +135,15 @@ int tbo_template_stages(const float* x0, const tbo_config* cfg, const tbo_templa
 int tbo_search(const float* x0, const tbo_config* cfg, const tbo_template* t,
                uint32_t count, uint32_t first_template_id, uint32_t series_id,
                int32_t nthreads, tbo_candidate* out, int64_t capacity, int64_t* n_total);
+
+/* O11 candidate grouping: the kept candidates (strongest of each group) in
+ * strength order into out (n records), their group sizes into group (may be
+ * NULL), their count into *n_kept.  max_ratio (1..64) bounds p and q of the
+ * harmonic ratios p/q; the tolerance is tol (0..2^20) sixteenths of a
+ * fundamental bin (1/(16 T)) plus ppm (0..1e6) parts per million of the
+ * target (p/q) F.  Returns 0, or -1 on bad arguments / allocation failure. */
+int tbo_distill(const tbo_candidate* in, int64_t n, int32_t max_ratio, int64_t tol, int64_t ppm,
+                tbo_candidate* out, int64_t* group, int64_t* n_kept);
 
 #ifdef __cplusplus
 }

@@ -9,6 +9,7 @@ import pytest
 import oracle
 from tests import test_oracle_end_to_end as E2E
 from tests import test_oracle_pins as PINS
+from tests import test_oracle_distill as DS
 from tests import test_oracle_series_whitening as SW
 
 MUTANTS = {
@@ -40,6 +41,16 @@ MUTANTS = {
     "series_levels_window": ("whiten_levels(p, nb, cfg->whiten_window, med, lev);",
                              "whiten_levels(p, nb, cfg->whiten_window + 1, med, lev);"),
     "series_search_drops_levels": ("        J.lev = lev;\n", ""),
+    "distill_tol_not_at_ratio": ("if (1000000 * d <= 1000000 * q * tol + ppm * p * fa) return 1;",
+                                 "if (1000000 * d <= 1000000 * tol + ppm * p * fa) return 1;"),
+    "distill_ppm_of_source": ("if (1000000 * d <= 1000000 * q * tol + ppm * p * fa) return 1;",
+                              "if (1000000 * d <= 1000000 * q * tol + ppm * q * fa) return 1;"),
+    "distill_across_series": ("    if (a->series_id != b->series_id) return 0;\n    int64_t fa = cand_F(a)",
+                              "    int64_t fa = cand_F(a)"),
+    "distill_weakest_first": ("if (a->sigma != b->sigma) return a->sigma > b->sigma;",
+                              "if (a->sigma != b->sigma) return a->sigma < b->sigma;"),
+    "distill_absorbed_kept": ("        if (absorbed[a]) continue;\n", ""),
+    "distill_fold_shift": ("return (int64_t)c->bin << (4 - c->log2_harm);", "return (int64_t)c->bin << c->log2_harm;"),
     "fold_pick_index": ("for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * hp)];",
                         "for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * h)];"),
 }
@@ -63,6 +74,10 @@ def _pins():
               E2E.test_injected_binary_peaks_at_true_template_and_frequency]:
         out.append(lambda f=f: f(None))
     out.append(lambda: PINS.test_fft_against_library(None, 14))
+    for f in [DS.test_hand_worked_example, DS.test_tolerance_is_measured_at_the_ratio,
+              DS.test_relative_tolerance_scales_with_the_target, DS.test_same_frequency_only]:
+        out.append(lambda f=f: f(None))
+    out.append(lambda: DS.test_greedy_matches_declarative_rule(None, 1, 16, 16, 0))
     for f in [SW.test_series_levels_of_an_impulse_are_flat, SW.test_series_levels_of_a_silent_series_are_zero,
               SW.test_series_medians_against_library_spectrum, SW.test_zero_orbit_matches_per_template_whitening,
               SW.test_levels_do_not_depend_on_the_template,
