@@ -144,6 +144,34 @@ def kernel_report(plan, n_avg: float, workload_name: str, tile: int, series_whit
     return per, roof
 
 
+def grouping_report(tb, cands, with_oracle: bool):
+    """Candidate grouping (tb_distill, host) of one step's candidates: time per
+    call and groups kept, for the default rule and with a 1e-3 relative
+    tolerance; the oracle's grouping of the same list timed beside it."""
+    rep = {"candidates": int(cands.size), "unit": "candidates/s"}
+    for name, kw in (("default", dict()), ("ppm1000", dict(ppm=1000))):
+        tb.tb_distill(cands, **kw)
+        reps = 20
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            kept, _ = tb.tb_distill(cands, **kw)
+        dt = (time.perf_counter() - t0) / reps
+        rep[name] = {"params": dict(max_ratio=16, tol=16, ppm=kw.get("ppm", 0)), "groups": int(kept.size),
+                     "ms": 1e3 * dt, "value": cands.size / dt if dt > 0 else None}
+    if with_oracle and cands.size:
+        import oracle
+
+        oracle.build()
+        o = np.zeros(cands.size, dtype=oracle.CANDIDATE_DTYPE)
+        for f in ("series_id", "template_id", "bin", "log2_harm", "power", "sigma", "freq_hz"):
+            o[f] = cands[f]
+        t0 = time.perf_counter()
+        ko, _ = oracle.distill(o)
+        dt = time.perf_counter() - t0
+        rep["oracle_default"] = {"groups": int(ko.size), "ms": 1e3 * dt, "value": cands.size / dt, "cores": 1}
+    return rep
+
+
 def stream_copy_gbs(plan, tb):
     import torch
 
@@ -201,11 +229,15 @@ def run_bank(args, tb, torch):
 
     chunks = np.array_split(np.arange(ntemp), max(1, args.split))
 
+    last = []
+
     def step():
         rids = [plan.submit(sid, w.templates[c[0]:c[-1] + 1], int(c[0])) for sid in sids for c in chunks if len(c)]
         ncand = 0
+        last.clear()
         for rid in rids:
             c, tot = plan.candidates(rid)
+            last.append(c)
             ncand += tot
             plan.release(rid)
         return ncand
@@ -242,6 +274,8 @@ def run_bank(args, tb, torch):
                                                      conf["tile_points"], args.series_whitening)
         out["stream_copy_gbs"] = stream_copy_gbs(plan, tb)
     plan.close()
+    out["grouping"] = grouping_report(tb, np.concatenate(last) if last else np.zeros(0, tb.CANDIDATE_DTYPE),
+                                      not args.no_cpu_baseline)
     if args.workload == "c4" and not args.no_plain:
         idx = list(range(min(4, len(w.series))))
         rates = plain_vs_batched(tb, w, idx, 256)

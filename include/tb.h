@@ -203,6 +203,26 @@ tb_status tb_profile_read(tb_plan_t plan, double ms[6], uint64_t launches[6], ui
  * copy.  A measurement utility: the practical HBM ceiling. */
 tb_status tb_stream_copy(tb_plan_t plan, void* dst, const void* src, uint64_t bytes, uint32_t reps, double* ms);
 
+/* Candidate grouping (App. A: the search software groups repeated detections
+ * of the same signal and keeps the strongest; the paper gives no rule, this
+ * is the library's).  Host arrays, no plan or device needed.
+ *   F = bin * 16 / 2^log2_harm: the fundamental in sixteenths of a bin.
+ *   Candidates are taken from the strongest (sigma descending, then series,
+ *   template, log2_harm, bin ascending).  One that no stronger kept candidate
+ *   has absorbed is kept, and absorbs every weaker, unabsorbed candidate of
+ *   the same series_id whose F is within tol + ppm 1e-6 (p/q) F_kept of
+ *   (p/q) F_kept for some integers 1 <= p, q <= max_ratio (1 = same frequency
+ *   only), decided exactly: 1e6 |q F - p F_kept| <= 1e6 q tol + ppm p F_kept.
+ *   tol is in sixteenths of a fundamental bin 1/T (16 = one bin).
+ * out (n records, must not overlap in) receives the kept candidates in
+ * strength order, group_size (may be NULL; n entries) how many candidates
+ * each one's group holds (itself included), *n_kept their number.  Any input
+ * order gives the same result.  TB_ERR_INVALID_ARG for NULL pointers with
+ * n > 0, n >= 2^32, max_ratio outside 1..64, tol > 2^20, ppm > 1e6, a
+ * log2_harm above 4 or a NaN sigma. */
+tb_status tb_distill(const tb_candidate* in, uint64_t n, uint32_t max_ratio, uint32_t tol, uint32_t ppm,
+                     tb_candidate* out, uint32_t* group_size, uint64_t* n_kept);
+
 #ifdef __cplusplus
 }
 #endif

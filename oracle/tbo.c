@@ -635,7 +635,7 @@ int tbo_distill(const tbo_candidate* in, int64_t n, int32_t max_ratio, int64_t t
         tol > (1 << 20) || ppm < 0 || ppm > 1000000)
         return -1;
     for (int64_t i = 0; i < n; ++i)
-        if (in[i].log2_harm < 0 || in[i].log2_harm > 4) return -1;
+        if (in[i].log2_harm < 0 || in[i].log2_harm > 4 || in[i].sigma != in[i].sigma) return -1;
     int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
     char* absorbed = (char*)calloc((size_t)(n ? n : 1), 1);
     if (!order || !absorbed) {

@@ -81,7 +81,7 @@ EXPORTS = [
     "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
-    "tb_set_budget",
+    "tb_set_budget", "tb_distill",
 ]
 
 
@@ -128,6 +128,7 @@ def _load():
     L.tb_stream_copy.argtypes = [vp, vp, vp, u64, u32, P(C.c_double)]
     L.tb_memory.argtypes = [vp, P(u64), P(u64)]
     L.tb_set_budget.argtypes = [vp, u64]
+    L.tb_distill.argtypes = [vp, u64, u32, u32, u32, vp, vp, P(u64)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tb_default_config", "tb_strerror"):
@@ -266,6 +267,19 @@ def tb_profile_read(plan: int):
     t = C.c_uint64(0)
     _check(_L.tb_profile_read(C.c_void_p(plan), _ptr(ms), _ptr(ln), C.byref(t)), "tb_profile_read")
     return ms, ln, int(t.value)
+
+
+def tb_distill(cands, max_ratio: int = 16, tol: int = 16, ppm: int = 0):
+    """Candidate grouping on the host: (kept candidates in strength order,
+    group sizes).  tol: sixteenths of a fundamental bin; ppm: parts per
+    million of the target frequency."""
+    c = np.ascontiguousarray(cands, dtype=CANDIDATE_DTYPE)
+    out = np.zeros(max(1, c.size), dtype=CANDIDATE_DTYPE)
+    grp = np.zeros(max(1, c.size), dtype=np.uint32)
+    nk = C.c_uint64(0)
+    _check(_L.tb_distill(_ptr(c), c.size, int(max_ratio), int(tol), int(ppm), _ptr(out), _ptr(grp), C.byref(nk)),
+           "tb_distill")
+    return out[: nk.value], grp[: nk.value]
 
 
 def tb_stream_copy(plan: int, dst: int, src: int, nbytes: int, reps: int = 10) -> float:

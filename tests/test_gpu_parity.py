@@ -291,3 +291,27 @@ def test_full_size_circular_survey(tb):
     sub = cg[np.isin(cg["template_id"], pick)]
     matched, exempt = R.check_candidates(sub, co, [oracle.threshold(1 << l, 6.0) for l in range(5)])
     _say("  tie-exempt %d, candidates matched %d exempt %d" % (ex, matched, exempt))
+
+
+def test_grouping_of_gpu_candidates(tb):
+    """The C1 candidate list from the GPU, grouped by the library and by the
+    oracle: identical kept records and group sizes; the injected pulsar's
+    strongest detection heads the largest group."""
+    w = synth.c1_tiny()
+    x, ts = w.series[0], w.tsamp
+    with tb.Plan(threshold_sigma=4.0) as plan:
+        sid = plan.load_series(x, ts)
+        cg = plan.search(sid, w.templates)
+    assert len(cg) > 100
+    o = np.zeros(cg.size, dtype=oracle.CANDIDATE_DTYPE)
+    for f in ("series_id", "template_id", "bin", "log2_harm", "power", "sigma", "freq_hz"):
+        o[f] = cg[f]
+    for kw in (dict(), dict(ppm=1000), dict(max_ratio=1, tol=0)):
+        kept, grp = tb.tb_distill(cg, **kw)
+        ko, go = oracle.distill(o, **kw)
+        ok = np.zeros(kept.size, dtype=oracle.CANDIDATE_DTYPE)
+        for f in ("series_id", "template_id", "bin", "log2_harm", "power", "sigma", "freq_hz"):
+            ok[f] = kept[f]
+        assert np.array_equal(ok, ko) and np.array_equal(grp.astype(np.int64), go), kw
+        assert kept[0]["sigma"] == cg["sigma"].max() and grp[0] == grp.max()
+    _say("grouping: %d candidates -> %d groups (ppm 1000)" % (len(cg), len(tb.tb_distill(cg, ppm=1000)[0])))
