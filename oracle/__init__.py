@@ -52,6 +52,7 @@ class Config(C.Structure):
         ("fmin_hz", C.c_double),
         ("fmax_hz", C.c_double),
         ("series_whitening", C.c_int32),
+        ("delay_model", C.c_int32),
     ]
 
 
@@ -138,6 +139,9 @@ def _bind(L):
     L.tbo_roemer_delay.argtypes = [P(Template), C.c_double]
     L.tbo_roemer_delay.restype = C.c_double
     L.tbo_resample_index.argtypes = [P(Template), C.c_int64, C.c_double, C.c_void_p, C.c_void_p]
+    L.tbo_roemer_delay_series.argtypes = [P(Template), C.c_double]
+    L.tbo_roemer_delay_series.restype = C.c_double
+    L.tbo_resample_index_model.argtypes = [P(Template), C.c_int64, C.c_double, C.c_int32, C.c_void_p, C.c_void_p]
     L.tbo_resample.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     L.tbo_dft_naive.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
     L.tbo_fft.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
@@ -192,9 +196,10 @@ def _templates_array(templates) -> np.ndarray:
 
 
 def config(n, tsamp, harm_max=16, whiten_window=4096, threshold_sigma=6.0, fmin_hz=1.0, fmax_hz=0.0,
-           series_whitening=False) -> Config:
+           series_whitening=False, delay_model=0) -> Config:
+    """delay_model: 0 BT with the Newton Kepler solve, 1 the App. B series."""
     return Config(int(n), float(tsamp), int(harm_max), int(whiten_window), float(threshold_sigma),
-                  float(fmin_hz), float(fmax_hz), int(bool(series_whitening)))
+                  float(fmin_hz), float(fmax_hz), int(bool(series_whitening)), int(delay_model))
 
 
 def mean_subtract(x: np.ndarray) -> np.ndarray:
@@ -220,6 +225,19 @@ def resample_index(t, n: int, tsamp: float):
     delta = np.empty(n, dtype=np.float64)
     src = np.empty(n, dtype=np.int64)
     lib().tbo_resample_index(C.byref(tt), int(n), float(tsamp), _ptr(delta), _ptr(src))
+    return src, delta
+
+
+def roemer_delay_series(t, time_s: float) -> float:
+    tt = _tmpl(t)
+    return lib().tbo_roemer_delay_series(C.byref(tt), float(time_s))
+
+
+def resample_index_model(t, n: int, tsamp: float, model: int):
+    tt = _tmpl(t)
+    delta = np.empty(n)
+    src = np.empty(n, dtype=np.int64)
+    lib().tbo_resample_index_model(C.byref(tt), int(n), float(tsamp), int(model), _ptr(delta), _ptr(src))
     return src, delta
 
 

@@ -81,6 +81,61 @@ void tbo_resample_index(const tbo_template* t, int64_t n, double tsamp,
     }
 }
 
+/* O3 with the App. B expansion (the paper's ELL7): cos E and sqrt(1-e^2) sin E
+ * replaced by their series in the mean anomaly, complete through e^6,
+ *   cos E = sum_{k=0..7} C_k(e) cos kM,  sqrt(1-e^2) sin E = sum_{k=1..7} S_k(e) sin kM,
+ * in the BT delay tau[(cos E - e) sin psi + sqrt(1-e^2) sin E cos psi].  No
+ * Kepler solve; the truncation leaves O(e^7) of tau. */
+static void appb_coefficients(double e, double* C, double* S)
+{
+    double e2 = e * e, e3 = e2 * e, e4 = e3 * e, e5 = e4 * e, e6 = e5 * e;
+    C[0] = -0.5 * e;
+    C[1] = 1.0 - 3.0 / 8.0 * e2 + 5.0 / 192.0 * e4 - 7.0 / 9216.0 * e6;
+    C[2] = 0.5 * e - 1.0 / 3.0 * e3 + 1.0 / 16.0 * e5;
+    C[3] = 3.0 / 8.0 * e2 - 45.0 / 128.0 * e4 + 567.0 / 5120.0 * e6;
+    C[4] = 1.0 / 3.0 * e3 - 2.0 / 5.0 * e5;
+    C[5] = 125.0 / 384.0 * e4 - 4375.0 / 9216.0 * e6;
+    C[6] = 27.0 / 80.0 * e5;
+    C[7] = 16807.0 / 46080.0 * e6;
+    S[0] = 0.0;
+    S[1] = 1.0 - 5.0 / 8.0 * e2 - 11.0 / 192.0 * e4 - 457.0 / 9216.0 * e6;
+    S[2] = 0.5 * e - 5.0 / 12.0 * e3 + 1.0 / 24.0 * e5;
+    S[3] = 3.0 / 8.0 * e2 - 51.0 / 128.0 * e4 + 543.0 / 5120.0 * e6;
+    S[4] = 1.0 / 3.0 * e3 - 13.0 / 30.0 * e5;
+    S[5] = 125.0 / 384.0 * e4 - 4625.0 / 9216.0 * e6;
+    S[6] = 27.0 / 80.0 * e5;
+    S[7] = 16807.0 / 46080.0 * e6;
+}
+
+double tbo_roemer_delay_series(const tbo_template* t, double time_s)
+{
+    double C[8], S[8];
+    appb_coefficients(t->ecc, C, S);
+    double Omega = 2.0 * M_PI / t->porb_s;
+    double M = Omega * time_s + t->alpha_rad;
+    double cosE = 0.0, sinE_b = 0.0;
+    for (int k = 0; k <= 7; ++k) {
+        cosE += C[k] * cos((double)k * M);
+        sinE_b += S[k] * sin((double)k * M);
+    }
+    return t->tau_lts * ((cosE - t->ecc) * sin(t->omega_rad) + sinE_b * cos(t->omega_rad));
+}
+
+void tbo_resample_index_model(const tbo_template* t, int64_t n, double tsamp, int32_t model,
+                              double* delta, int64_t* src)
+{
+    if (model == 0) {
+        tbo_resample_index(t, n, tsamp, delta, src);
+        return;
+    }
+    double d0 = tbo_roemer_delay_series(t, 0.0);
+    for (int64_t j = 0; j < n; ++j) {
+        double dj = (tbo_roemer_delay_series(t, (double)j * tsamp) - d0) / tsamp;
+        if (delta) delta[j] = dj;
+        if (src) src[j] = j - (int64_t)rint(dj);
+    }
+}
+
 /* Samples the demodulated series needs from before the start or after the end
  * of the observation are zero, i.e. the (removed) mean. */
 void tbo_resample(const float* x0, int64_t n, const int64_t* src, double* y)
@@ -390,6 +445,7 @@ static int valid_cfg(const tbo_config* c)
         && c->harm_max != 16)
         return 0;
     if (c->series_whitening != 0 && c->series_whitening != 1) return 0;
+    if (c->delay_model != 0 && c->delay_model != 1) return 0;
     return 1;
 }
 
@@ -400,7 +456,7 @@ static void front_end(const float* x0, const tbo_config* c, const tbo_template* 
                       double* med, work_t* w)
 {
     int64_t n = c->n, nb = n / 2 + 1;
-    tbo_resample_index(t, n, c->tsamp, NULL, w->src);
+    tbo_resample_index_model(t, n, c->tsamp, c->delay_model, NULL, w->src);
     tbo_resample(x0, n, w->src, w->y);
     if (n <= 4096) tbo_dft_naive(w->y, n, w->re, w->im);
     else tbo_fft(w->y, n, w->re, w->im);

@@ -63,6 +63,8 @@ typedef struct {
     int32_t series_whitening; /* 0: each template whitened by its own block
                                  medians; 1: levels taken once from the
                                  series' own spectrum (tbo_series_levels) */
+    int32_t delay_model;      /* 0: BT with the Newton Kepler solve; 1: the
+                                 App. B series (tbo_roemer_delay_series) */
 } tbo_config;
 
 typedef struct {
@@ -89,6 +91,14 @@ double tbo_roemer_delay(const tbo_template* t, double time_s);
  * and src_j = j - rint(delta_j). */
 void tbo_resample_index(const tbo_template* t, int64_t n, double tsamp,
                         double* delta, int64_t* src);
+
+/* O3 through the App. B series of cos E and sqrt(1-e^2) sin E in the mean
+ * anomaly (complete through e^6, the paper's ELL7), no Kepler solve. */
+double tbo_roemer_delay_series(const tbo_template* t, double time_s);
+
+/* O4 with the delay of model 0 (BT, Newton) or 1 (App. B series). */
+void tbo_resample_index_model(const tbo_template* t, int64_t n, double tsamp, int32_t model,
+                              double* delta, int64_t* src);
 
 /* O4: y_j = x0[src_j] inside [0, n), else 0. */
 void tbo_resample(const float* x0, int64_t n, const int64_t* src, double* y);

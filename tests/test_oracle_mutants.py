@@ -10,6 +10,7 @@ import oracle
 from tests import test_oracle_end_to_end as E2E
 from tests import test_oracle_pins as PINS
 from tests import test_oracle_distill as DS
+from tests import test_oracle_ell as ELL
 from tests import test_oracle_series_whitening as SW
 
 MUTANTS = {
@@ -51,6 +52,11 @@ MUTANTS = {
                               "if (a->sigma != b->sigma) return a->sigma < b->sigma;"),
     "distill_absorbed_kept": ("        if (absorbed[a]) continue;\n", ""),
     "distill_fold_shift": ("return (int64_t)c->bin << (4 - c->log2_harm);", "return (int64_t)c->bin << c->log2_harm;"),
+    "appb_C1_e6_sign": ("- 7.0 / 9216.0 * e6;", "+ 7.0 / 9216.0 * e6;"),
+    "appb_S3_e4": ("S[3] = 3.0 / 8.0 * e2 - 51.0 / 128.0 * e4", "S[3] = 3.0 / 8.0 * e2 - 45.0 / 128.0 * e4"),
+    "appb_C0_dropped": ("    for (int k = 0; k <= 7; ++k) {\n        cosE", "    for (int k = 1; k <= 7; ++k) {\n        cosE"),
+    "appb_sin_cos_swapped": ("sinE_b += S[k] * sin((double)k * M);", "sinE_b += S[k] * cos((double)k * M);"),
+    "series_no_zero_offset": ("double d0 = tbo_roemer_delay_series(t, 0.0);", "double d0 = 0.0;"),
     "fold_pick_index": ("for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * hp)];",
                         "for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * h)];"),
 }
@@ -74,6 +80,10 @@ def _pins():
               E2E.test_injected_binary_peaks_at_true_template_and_frequency]:
         out.append(lambda f=f: f(None))
     out.append(lambda: PINS.test_fft_against_library(None, 14))
+    out.append(lambda: ELL.test_appendix_b_coefficients_are_the_bessel_taylor_polynomials(None, 0.3))
+    out.append(lambda: ELL.test_series_delay_within_truncation_of_exact(None, 0.1))
+    for f in [ELL.test_zero_eccentricity_is_the_circular_bt_delay, ELL.test_series_indices_follow_the_exact_delay]:
+        out.append(lambda f=f: f(None))
     for f in [DS.test_hand_worked_example, DS.test_tolerance_is_measured_at_the_ratio,
               DS.test_relative_tolerance_scales_with_the_target, DS.test_same_frequency_only]:
         out.append(lambda f=f: f(None))
