@@ -101,14 +101,14 @@ def traffic_record(kernel: str, workload_name: str):
     return rec
 
 
-def cpu_baseline(w, seconds_hint: float, series_whitening: bool = False):
+def cpu_baseline(w, seconds_hint: float, series_whitening: bool = False, delay_series: bool = False):
     import oracle
 
     oracle.build()
     threads = max(1, min(os.cpu_count() or 1, 16))
     x = w.series[0]
     n = x.size
-    cfg = oracle.config(n, w.tsamp, series_whitening=series_whitening)
+    cfg = oracle.config(n, w.tsamp, series_whitening=series_whitening, delay_model=int(delay_series))
     x0 = oracle.mean_subtract(x)
     t0 = time.perf_counter()
     oracle.search(x0, cfg, w.templates[:1], nthreads=1)
@@ -215,14 +215,17 @@ def run_bank(args, tb, torch):
     conf["requests_per_series"] = max(1, args.split)
     if args.series_whitening:
         conf["whitening"] = "once per series (levels from the series' own spectrum)"
+    if args.delay_series:
+        conf["delay"] = "App. B series of cos E and sqrt(1-e^2) sin E (ELL7), no Kepler solve"
     load_flags = tb.TB_SERIES_WHITENING if args.series_whitening else tb.TB_MEM_HOST
-    profile_name = args.workload + ("_series_whitening" if args.series_whitening else "")
+    profile_name = args.workload + ("_series_whitening" if args.series_whitening else "") + \
+        ("_delay_series" if args.delay_series else "")
     # one series: waves of one stream keep the device busy (lanes add no throughput there);
     # several series: one request per series, spread over four lanes
     lanes = args.lanes or (4 if len(w.series) > 1 else 1)
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
                    threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18,
-                   tile_points=args.tile)
+                   tile_points=args.tile, flags=tb.TB_DELAY_SERIES if args.delay_series else 0)
     sids = [plan.load_series(s, w.tsamp, flags=load_flags) for s in w.series]
     ntemp = len(w.templates)
     nitems = ntemp * len(sids)
@@ -263,6 +266,8 @@ def run_bank(args, tb, torch):
     metric = METRIC if args.workload == "c2" else "templates/s (%s)" % args.workload
     if args.series_whitening:
         metric += " [whitened once per series]"
+    if args.delay_series:
+        metric += " [series delay]"
     out = {"metric": metric, "value": value,
            "unit": "templates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -285,7 +290,7 @@ def run_bank(args, tb, torch):
         out["batched_vs_plain"] = rates["batched"] / rates["plain"]
     if not args.no_cpu_baseline and args.workload in ("c1", "c2", "c3"):
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.series_whitening)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, args.series_whitening, args.delay_series)
     return out
 
 
@@ -359,6 +364,8 @@ def main():
     ap.add_argument("--tile", type=int, default=0, help="FFT points per workgroup, 8192 or 16384 (0 = library default)")
     ap.add_argument("--series-whitening", action="store_true",
                     help="whiten once per series (levels from its own spectrum) instead of per template")
+    ap.add_argument("--delay-series", action="store_true",
+                    help="Roemer delay from the App. B series (ELL7) instead of BT with a Newton solve")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")

@@ -48,6 +48,14 @@ typedef enum {
     TB_ERR_UNKNOWN_ID = -7   /* no such series or request */
 } tb_status;
 
+/* tb_config.flags.  TB_DELAY_SERIES: the Roemer delay of every template is
+ * taken from the series of cos E and sqrt(1-e^2) sin E in the mean anomaly
+ * with the App. B coefficients (complete through e^6; the ELL7 model of Sec.
+ * 2.2 and App. A.1) instead of the BT delay with a Newton solve of Kepler's
+ * equation.  It differs from the BT delay by O(e^7) of tau (about 1.3 e^7 tau
+ * at most; 1e-7 tau at e = 0.1) and equals it for e = 0. */
+enum { TB_DELAY_SERIES = 1 };
+
 /* tb_load_series flags: where data lives (one of the two), optionally ORed
  * with TB_SERIES_WHITENING. */
 enum { TB_MEM_HOST = 0, TB_MEM_DEVICE = 1, TB_SERIES_WHITENING = 2 };
@@ -66,7 +74,7 @@ typedef struct {
     int32_t device;            /* HIP device ordinal; the plan makes it current on each call */
     uint32_t lanes;            /* streams requests are spread over (1..16); work on different
                                   lanes overlaps on the device.  Lane 0 is `stream`. */
-    uint32_t flags;            /* reserved, 0 */
+    uint32_t flags;            /* 0, or TB_DELAY_SERIES */
     uint32_t tile_points;      /* FFT points per workgroup: 8192 (two workgroups per compute
                                   unit) or 16384 (one); 0 = the plan's choice (8192, and
                                   16384 for series of 2^24 samples) */

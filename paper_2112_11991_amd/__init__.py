@@ -28,6 +28,7 @@ TB_ERR_UNKNOWN_ID = -7
 TB_MEM_HOST = 0
 TB_MEM_DEVICE = 1
 TB_SERIES_WHITENING = 2  # OR into the load flags: whiten once from the series' own spectrum
+TB_DELAY_SERIES = 1  # tb_config.flags: Roemer delay from the App. B series (ELL7) instead of BT-Newton
 
 
 class TbConfig(C.Structure):

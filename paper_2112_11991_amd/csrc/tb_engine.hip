@@ -405,6 +405,22 @@ PeakParams peak_params(tb_plan_t p, int64_t n, double tsamp, uint32_t series_id,
     return pp;
 }
 
+int delay_model(const tb_plan_t p) { return (p->cfg.flags & TB_DELAY_SERIES) ? 1 : 0; }
+
+// Sample indices stay 32-bit: the delay swing may not exceed 2^29 samples.
+// |F| <= 1 + e for the BT delay, e + sum |C_k| + |S_k| for the series.
+bool delay_fits(const tb_plan_t p, const tb_template& t, double tsamp)
+{
+    double bound = 1.0 + t.ecc;
+    if (delay_model(p)) {
+        double C[8], S[8];
+        series_coefficients(t.ecc, C, S);
+        bound = t.ecc;
+        for (int k = 0; k < 8; ++k) bound += std::fabs(C[k]) + std::fabs(S[k]);
+    }
+    return 2.0 * t.tau_lts * bound / tsamp <= (double)(1 << 29);
+}
+
 bool valid_template(const tb_template& t)
 {
     return std::isfinite(t.porb_s) && std::isfinite(t.tau_lts) && std::isfinite(t.alpha_rad) &&
@@ -595,7 +611,8 @@ tb_status tb_plan(const tb_config* cfg, tb_plan_t* out)
     if (!std::isfinite(c.threshold_sigma) || !std::isfinite(c.fmin_hz) || !std::isfinite(c.fmax_hz) ||
         c.fmin_hz < 0.0 || c.fmax_hz < 0.0)
         return TB_ERR_INVALID_ARG;
-    if (c.ring_capacity == 0 || c.ring_capacity > 0xffffffffull || c.batch_templates > 4096 || c.flags ||
+    if (c.ring_capacity == 0 || c.ring_capacity > 0xffffffffull || c.batch_templates > 4096 ||
+        (c.flags & ~(uint32_t)TB_DELAY_SERIES) ||
         (c.tile_points != 0 && c.tile_points != 8192 && c.tile_points != 16384) || c.lanes < 1 || c.lanes > 16)
         return TB_ERR_INVALID_ARG;
     int ndev = 0;
@@ -696,7 +713,7 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
     // order, then a template without orbit for the series levels
     float* staging = nullptr;
     const size_t tmpl_off = ((2 * sizeof(float) * n) + 255) & ~(size_t)255;
-    if (hipMalloc(&staging, tmpl_off + 256) != hipSuccess) {
+    if (hipMalloc(&staging, tmpl_off + 256 + sizeof(TmplDev)) != hipSuccess) {
         hipFree(r.d);
         p->held -= r.bytes;
         return TB_ERR_OOM;
@@ -714,9 +731,9 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
         // tau = 0: the demodulation reads every sample where it is
         static const tb_template still = {1.0, 0.0, 0.0, 0.0, 0.0};
         tb_template* d_t = (tb_template*)((char*)staging + tmpl_off);
-        TmplDev* d_tm = (TmplDev*)((char*)staging + tmpl_off + 128);
+        TmplDev* d_tm = (TmplDev*)((char*)staging + tmpl_off + 256);
         e = hipMemcpyAsync(d_t, &still, sizeof(still), hipMemcpyHostToDevice, p->stream);
-        if (e == hipSuccess) e = launch_template_prep(d_t, 1, d_tm, p->stream);
+        if (e == hipSuccess) e = launch_template_prep(d_t, 1, d_tm, 0, p->stream);
         if (e == hipSuccess) e = launch_series_levels(*g, r.d, tsamp, d_tm, *ws, r.med, r.fac, p->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -757,9 +774,8 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
     if (sit == p->series.end()) return TB_ERR_UNKNOWN_ID;
     TB_TRY(hipSetDevice(p->cfg.device));
     const SeriesRec& sr = sit->second;
-    // sample indices stay 32-bit: the delay may not exceed 2^29 samples
     for (uint32_t i = 0; i < count; ++i)
-        if (!(2.0 * t[i].tau_lts * (1.0 + t[i].ecc) / sr.tsamp <= (double)(1 << 29))) return TB_ERR_INVALID_ARG;
+        if (!delay_fits(p, t[i], sr.tsamp)) return TB_ERR_INVALID_ARG;
     Geometry* g = nullptr;
     Slots* ws = nullptr;
     tb_status st;
@@ -809,7 +825,7 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
         hipEventRecord(r.ev0, stream) != hipSuccess || launch_fill_u32(counter, 0u, 1, stream) != hipSuccess ||
         (count && hipMemcpyAsync(d_t, r.h_t, sizeof(tb_template) * count, hipMemcpyHostToDevice, stream) !=
                       hipSuccess) ||
-        launch_template_prep(d_t, count, d_tm, stream) != hipSuccess) {
+        launch_template_prep(d_t, count, d_tm, delay_model(p), stream) != hipSuccess) {
         hipStreamSynchronize(stream);
         free_request(p, r);
         p->held -= r.bytes;
@@ -1052,7 +1068,7 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     if (sit == p->series.end()) return TB_ERR_UNKNOWN_ID;
     TB_TRY(hipSetDevice(p->cfg.device));
     const SeriesRec& sr = sit->second;
-    if (!(2.0 * t->tau_lts * (1.0 + t->ecc) / sr.tsamp <= (double)(1 << 29))) return TB_ERR_INVALID_ARG;
+    if (!delay_fits(p, *t, sr.tsamp)) return TB_ERR_INVALID_ARG;
     Geometry* g = nullptr;
     Slots* ws = nullptr;
     tb_status st;
@@ -1060,8 +1076,11 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     if ((st = get_slots(p, 0, *g, &ws))) return st;
     int nfold = ilog2(p->cfg.harm_max) + 1;
     size_t nb = (size_t)g->M + 1;
-    size_t need = 256 + 256 + sizeof(uint4) * 16 + sizeof(int32_t) * (size_t)sr.n + sizeof(float) * nfold * nb +
-                  sizeof(float) * nb;
+    // [0, 256) prepared template, [256, 320) template, [512, 768) counter,
+    // [768, 1024) ring, then indices, fold sums, power
+    static_assert(sizeof(TmplDev) <= 256, "inspection layout");
+    const size_t off_src = 1024;
+    size_t need = off_src + sizeof(int32_t) * (size_t)sr.n + sizeof(float) * nfold * nb + sizeof(float) * nb;
     char* d = nullptr;
     tb_template* ht = nullptr;
     if (hipMalloc(&d, need) != hipSuccess) return TB_ERR_OOM;
@@ -1071,11 +1090,11 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     }
     *ht = *t;
     TmplDev* d_tm = (TmplDev*)d;
-    tb_template* d_t = (tb_template*)(d + 128);
-    uint32_t* counter = (uint32_t*)(d + 256);
-    uint4* ring = (uint4*)(d + 512);
+    tb_template* d_t = (tb_template*)(d + 256);
+    uint32_t* counter = (uint32_t*)(d + 512);
+    uint4* ring = (uint4*)(d + 768);
     Inspect ins;
-    ins.src = (int32_t*)(d + 512 + sizeof(uint4) * 16);
+    ins.src = (int32_t*)(d + off_src);
     ins.sums = (float*)((char*)ins.src + sizeof(int32_t) * (size_t)sr.n);
     ins.power = ins.sums + (size_t)nfold * nb;
     float* const d_power = ins.power;
@@ -1083,7 +1102,7 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
     st = TB_OK;
     if (launch_fill_u32(counter, 0u, 1, p->stream) != hipSuccess ||
         hipMemcpyAsync(d_t, ht, sizeof(tb_template), hipMemcpyHostToDevice, p->stream) != hipSuccess ||
-        launch_template_prep(d_t, 1, d_tm, p->stream) != hipSuccess)
+        launch_template_prep(d_t, 1, d_tm, delay_model(p), p->stream) != hipSuccess)
         st = TB_ERR_DEVICE;
     if (!st && sr.fac && power) {
         // a series whitened once: pass 2 of the search stores whitened power,

@@ -14,12 +14,41 @@ namespace tb {
 
 // Per-template constants, prepared on the device from a tb_template:
 // Omega = 2 pi / P_orb, the Roemer-delay factors of the BT model (App. A.1)
-// and the zero offset Delta(0) of Algorithm 1.
+// and the zero offset Delta(0) of Algorithm 1.  With the series delay
+// (model 1) also sin(psi) C_k and cos(psi) S_k of the App. B expansion and
+// sum_k k^5 (|C_k| + |S_k|), the bound on the fifth derivative in M.
 struct TmplDev {
     double omega, alpha, tau, ecc;
     double sinw, cosw, beta, d0;
+    double ca[8], sb[8];
+    double g5;
+    int32_t model, pad;
 };
-static_assert(sizeof(TmplDev) == 64, "TmplDev layout");
+static_assert(sizeof(TmplDev) == 208, "TmplDev layout");
+
+// App. B coefficients C_0..C_7 and S_0..S_7 (S_0 = 0) of
+//   cos E = sum C_k(e) cos kM,  sqrt(1-e^2) sin E = sum S_k(e) sin kM,
+// complete through e^6.
+__host__ __device__ inline void series_coefficients(double e, double* C, double* S)
+{
+    const double e2 = e * e, e3 = e2 * e, e4 = e3 * e, e5 = e4 * e, e6 = e5 * e;
+    C[0] = -e / 2.0;
+    C[1] = 1.0 - (3.0 / 8.0) * e2 + (5.0 / 192.0) * e4 - (7.0 / 9216.0) * e6;
+    C[2] = e / 2.0 - e3 / 3.0 + e5 / 16.0;
+    C[3] = (3.0 / 8.0) * e2 - (45.0 / 128.0) * e4 + (567.0 / 5120.0) * e6;
+    C[4] = e3 / 3.0 - (2.0 / 5.0) * e5;
+    C[5] = (125.0 / 384.0) * e4 - (4375.0 / 9216.0) * e6;
+    C[6] = (27.0 / 80.0) * e5;
+    C[7] = (16807.0 / 46080.0) * e6;
+    S[0] = 0.0;
+    S[1] = 1.0 - (5.0 / 8.0) * e2 - (11.0 / 192.0) * e4 - (457.0 / 9216.0) * e6;
+    S[2] = e / 2.0 - (5.0 / 12.0) * e3 + e5 / 24.0;
+    S[3] = (3.0 / 8.0) * e2 - (51.0 / 128.0) * e4 + (543.0 / 5120.0) * e6;
+    S[4] = e3 / 3.0 - (13.0 / 30.0) * e5;
+    S[5] = (125.0 / 384.0) * e4 - (4625.0 / 9216.0) * e6;
+    S[6] = (27.0 / 80.0) * e5;
+    S[7] = (16807.0 / 46080.0) * e6;
+}
 
 // Two-pass FFT geometry of a real series of n = 2M samples packed as M
 // complex points, M = R * S.  Each workgroup holds min(TE, M) points, TE the
@@ -88,7 +117,8 @@ struct Inspect {
     float* sums = nullptr;   // nfold x (M + 1)
 };
 
-hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, hipStream_t s);
+// model: 0 BT with the Newton Kepler solve, 1 the App. B series.
+hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, int model, hipStream_t s);
 hipError_t launch_mean_subtract(const float* in, float* out, int64_t n, double* partial, hipStream_t s);
 // Kernel classes timed by the plan's profiler, in launch order.
 enum { K_POLY = 0, K_PASS1 = 1, K_PASS2 = 2, K_MEDIAN = 3, K_WHITEN = 4, K_HARMSUM = 5, K_CLASSES = 6 };

@@ -55,9 +55,24 @@ __device__ __forceinline__ double kepler_E(double M, double e)
     return E;
 }
 
+// The same delay through the App. B series (model 1): sum over k of
+// sin(psi) C_k cos kM + cos(psi) S_k sin kM, minus e sin(psi); no Kepler solve.
+__device__ __forceinline__ double series_F(const TmplDev& p, double M)
+{
+    double F = p.ca[0] - p.ecc * p.sinw;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        double s, c;
+        sincos((double)k * M, &s, &c);
+        F += p.ca[k] * c + p.sb[k] * s;
+    }
+    return F;
+}
+
 __device__ __forceinline__ double roemer(const TmplDev& p, double t)
 {
     double M = p.omega * t + p.alpha;
+    if (p.model) return p.tau * series_F(p, M);
     double E = kepler_E(M, p.ecc);
     double s, c;
     sincos(E, &s, &c);
@@ -80,7 +95,8 @@ __device__ __forceinline__ int rint_i32(double d)
     return __double2loint(t);
 }
 
-__global__ void k_template_prep(const tb_template* __restrict__ t, uint32_t count, TmplDev* __restrict__ out)
+__global__ void k_template_prep(const tb_template* __restrict__ t, uint32_t count, TmplDev* __restrict__ out,
+                                int model)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
@@ -93,6 +109,17 @@ __global__ void k_template_prep(const tb_template* __restrict__ t, uint32_t coun
     d.sinw = sin(a.omega_rad);
     d.cosw = cos(a.omega_rad);
     d.beta = sqrt(1.0 - a.ecc * a.ecc);
+    d.model = model;
+    d.pad = 0;
+    double C[8], S[8];
+    series_coefficients(a.ecc, C, S);
+    d.g5 = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        d.ca[k] = d.sinw * C[k];
+        d.sb[k] = d.cosw * S[k];
+        const double k5 = (double)(k * k * k * k * k);
+        d.g5 += k5 * (fabs(C[k]) + fabs(S[k]));
+    }
     d.d0 = 0.0;
     d.d0 = roemer(d, 0.0);
     out[i] = d;
@@ -357,15 +384,48 @@ __device__ __forceinline__ bool poly_ok(const TmplDev& p, double tsamp, double U
 {
     const double A = p.tau / tsamp, Wp = p.omega * tsamp, e = p.ecc, om = 1.0 - e;
     const double om3 = om * om * om;
-    const double g5 = 3.0 * (1.0 + e) * (1.0 + e) / (om3 * om3 * om3);
+    // |F^(5)| in M: the BT bound, or sum k^5 (|C_k| + |S_k|) for the series
+    const double g5 = p.model ? p.g5 : 3.0 * (1.0 + e) * (1.0 + e) / (om3 * om3 * om3);
     const double w5 = Wp * Wp * Wp * Wp * Wp, u5 = U * U * U * U * U;
     return A * w5 * g5 * u5 / 120.0 <= 1e-11;
+}
+
+// Series model: F^(m)(M) = sum_k k^m [a_k cos^(m)(kM) + b_k sin^(m)(kM)] with
+// a_k = sin(psi) C_k, b_k = cos(psi) S_k.
+__device__ __forceinline__ void series_derivatives(const TmplDev& p, double M, double (&F)[5])
+{
+    F[0] = p.ca[0] - p.ecc * p.sinw;
+    F[1] = F[2] = F[3] = F[4] = 0.0;
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        double s, c;
+        sincos((double)k * M, &s, &c);
+        const double a = p.ca[k], b = p.sb[k], kk = (double)k;
+        const double ac = a * c, as = a * s, bc = b * c, bs = b * s;
+        F[0] += ac + bs;
+        F[1] += kk * (bc - as);
+        F[2] -= kk * kk * (ac + bs);
+        F[3] += kk * kk * kk * (as - bc);
+        F[4] += kk * kk * kk * kk * (ac + bs);
+    }
 }
 
 __device__ __forceinline__ DelayPoly delay_poly(const TmplDev& p, double tsamp, int64_t jc)
 {
     const double e = p.ecc;
     const double M = p.omega * ((double)jc * tsamp) + p.alpha;
+    const double w = p.omega, ts = tsamp;
+    DelayPoly r;
+    if (p.model) {
+        double F[5];
+        series_derivatives(p, M, F);
+        r.c0 = (p.tau * F[0] - p.d0) / ts;
+        r.c1 = p.tau * w * F[1];
+        r.c2 = p.tau * w * w * ts * F[2] * 0.5;
+        r.c3 = p.tau * w * w * w * ts * ts * F[3] * (1.0 / 6.0);
+        r.c4 = p.tau * w * w * w * w * ts * ts * ts * F[4] * (1.0 / 24.0);
+        return r;
+    }
     const double E = kepler_E(M, e);
     double sE, cE;
     sincos(E, &sE, &cE);
@@ -383,8 +443,6 @@ __device__ __forceinline__ DelayPoly delay_poly(const TmplDev& p, double tsamp, 
     const double F3 = -FE * E1 * E1 * E1 + 3.0 * FEE * E1 * E2 + FE * E3;
     const double F4 = -FEE * E1 * E1 * E1 * E1 - 6.0 * FE * E1 * E1 * E2 + FEE * (3.0 * E2 * E2 + 4.0 * E1 * E3) +
                       FE * E4;
-    const double w = p.omega, ts = tsamp;
-    DelayPoly r;
     r.c0 = (p.tau * F - p.d0) / ts;
     r.c1 = p.tau * w * F1;
     r.c2 = p.tau * w * w * ts * F2 * 0.5;
@@ -439,7 +497,7 @@ __device__ __attribute__((noinline)) void gather_exact(const float* __restrict__
                                                        int32_t* __restrict__ src_out)
 {
     constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1;
-    const TmplDev p = *tp;
+    const TmplDev& p = *tp;
 #pragma unroll 1
     for (int e = threadIdx.x; e < C1 * S; e += T) {
         const int j = 2 * (c0 + (e % C1) + R * (e / C1));
@@ -1073,10 +1131,10 @@ hipError_t launch_fft2(const Geometry& g, int nslots, const Slots& ws, const flo
 
 int harmsum_tile() { return HT; }
 
-hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, hipStream_t s)
+hipError_t launch_template_prep(const tb_template* t, uint32_t count, TmplDev* out, int model, hipStream_t s)
 {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_template_prep, dim3((count + 127) / 128), dim3(128), 0, s, t, count, out);
+    hipLaunchKernelGGL(k_template_prep, dim3((count + 127) / 128), dim3(128), 0, s, t, count, out, model);
     return hipGetLastError();
 }
 

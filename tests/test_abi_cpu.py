@@ -41,7 +41,7 @@ def test_default_config_and_strerror():
     "field,value",
     [("max_log2n", 9), ("max_log2n", 25), ("harm_max", 3), ("harm_max", 32), ("whiten_window", 0),
      ("whiten_window", 8193), ("threshold_sigma", float("nan")), ("fmin_hz", -1.0), ("ring_capacity", 0),
-     ("flags", 1), ("tile_points", 4096), ("tile_points", 12288), ("lanes", 0), ("lanes", 17)],
+     ("flags", 2), ("flags", 0x80000001), ("tile_points", 4096), ("tile_points", 12288), ("lanes", 0), ("lanes", 17)],
 )
 def test_plan_rejects_bad_config(field, value):
     import paper_2112_11991_amd as tb
