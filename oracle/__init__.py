@@ -53,6 +53,9 @@ class Config(C.Structure):
         ("fmax_hz", C.c_double),
         ("series_whitening", C.c_int32),
         ("delay_model", C.c_int32),
+        ("nzap", C.c_int32),
+        ("zap_lo_hz", C.c_void_p),
+        ("zap_hi_hz", C.c_void_p),
     ]
 
 
@@ -149,6 +152,8 @@ def _bind(L):
     L.tbo_whiten.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p]
     L.tbo_series_levels.argtypes = [C.c_void_p, P(Config), C.c_void_p, C.c_void_p]
     L.tbo_series_levels.restype = C.c_int
+    L.tbo_zap.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p, C.c_int32]
+    L.tbo_zap.restype = None
     L.tbo_harmsum.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
     L.tbo_threshold.argtypes = [C.c_int32, C.c_double]
     L.tbo_threshold.restype = C.c_double
@@ -196,10 +201,18 @@ def _templates_array(templates) -> np.ndarray:
 
 
 def config(n, tsamp, harm_max=16, whiten_window=4096, threshold_sigma=6.0, fmin_hz=1.0, fmax_hz=0.0,
-           series_whitening=False, delay_model=0) -> Config:
-    """delay_model: 0 BT with the Newton Kepler solve, 1 the App. B series."""
-    return Config(int(n), float(tsamp), int(harm_max), int(whiten_window), float(threshold_sigma),
-                  float(fmin_hz), float(fmax_hz), int(bool(series_whitening)), int(delay_model))
+           series_whitening=False, delay_model=0, zap=()) -> Config:
+    """delay_model: 0 BT with the Newton Kepler solve, 1 the App. B series.
+    zap: (lo_hz, hi_hz) intervals whose bins are zeroed after whitening."""
+    c = Config(int(n), float(tsamp), int(harm_max), int(whiten_window), float(threshold_sigma),
+               float(fmin_hz), float(fmax_hz), int(bool(series_whitening)), int(delay_model))
+    if len(zap):
+        z = np.ascontiguousarray(np.asarray(zap, dtype=np.float64).reshape(-1, 2).T)
+        c._zap = z  # keeps the arrays alive with the config
+        c.nzap = z.shape[1]
+        c.zap_lo_hz = z[0].ctypes.data
+        c.zap_hi_hz = z[1].ctypes.data
+    return c
 
 
 def mean_subtract(x: np.ndarray) -> np.ndarray:

@@ -323,6 +323,19 @@ int tbo_series_levels(const float* x0, const tbo_config* cfg, double* med, doubl
     return rc;
 }
 
+/* Birdie zapping (App. A and Sec. 5.2 list Fourier birdie zapping among the
+ * per-series steps; no rule is given): known interference frequencies are
+ * removed from the search by zeroing the whitened power of the bins whose
+ * frequency k / T lies in a listed interval, before the harmonic sum. */
+void tbo_zap(double* phat, int64_t nbins, double T, const double* lo_hz, const double* hi_hz, int32_t count)
+{
+    for (int32_t i = 0; i < count; ++i) {
+        double lo = ceil(lo_hz[i] * T), hi = floor(hi_hz[i] * T);
+        for (int64_t k = 1; k < nbins; ++k)
+            if ((double)k >= lo && (double)k <= hi) phat[k] = 0.0;
+    }
+}
+
 /* ---------------------------------------------------------------- O8 ---- */
 /* Incoherent harmonic sum S_L = sum_{n <= 2^L} P_n (Sec. 2.1) on the bin grid:
  * bin k of fold h holds the h-th harmonic of a fundamental at k/h bins, and
@@ -446,6 +459,7 @@ static int valid_cfg(const tbo_config* c)
         return 0;
     if (c->series_whitening != 0 && c->series_whitening != 1) return 0;
     if (c->delay_model != 0 && c->delay_model != 1) return 0;
+    if (c->nzap < 0 || (c->nzap > 0 && (!c->zap_lo_hz || !c->zap_hi_hz))) return 0;
     return 1;
 }
 
@@ -463,6 +477,7 @@ static void front_end(const float* x0, const tbo_config* c, const tbo_template* 
     tbo_power(w->re, w->im, nb, w->p);
     if (lev) whiten_apply(w->p, nb, lev, w->phat);
     else tbo_whiten(w->p, nb, c->whiten_window, med, w->phat);
+    tbo_zap(w->phat, nb, (double)n * c->tsamp, c->zap_lo_hz, c->zap_hi_hz, c->nzap);
 }
 
 int tbo_template_stages(const float* x0, const tbo_config* cfg, const tbo_template* t,

@@ -65,6 +65,9 @@ typedef struct {
                                  series' own spectrum (tbo_series_levels) */
     int32_t delay_model;      /* 0: BT with the Newton Kepler solve; 1: the
                                  App. B series (tbo_roemer_delay_series) */
+    int32_t nzap;             /* birdies: whitened powers of bins k with    */
+    const double* zap_lo_hz;  /* zap_lo_hz[i] <= k / T <= zap_hi_hz[i]      */
+    const double* zap_hi_hz;  /* are set to 0 (tbo_zap); nzap = 0: none     */
 } tbo_config;
 
 typedef struct {
@@ -120,6 +123,11 @@ void tbo_whiten(const double* p, int64_t nbins, int64_t w, double* med, double* 
  * of x0 itself.  A template searched with cfg->series_whitening = 1 has
  * P^_k = P_k ln2 / m(k).  Returns 0, or -1 on allocation failure. */
 int tbo_series_levels(const float* x0, const tbo_config* cfg, double* med, double* lev);
+
+/* O7b birdie zapping: phat_k = 0 for every bin k (1..nbins-1) with
+ * lo_hz[i] <= k / T <= hi_hz[i] for some i, T = n tsamp; i.e. k from
+ * ceil(lo T) to floor(hi T). */
+void tbo_zap(double* phat, int64_t nbins, double T, const double* lo_hz, const double* hi_hz, int32_t count);
 
 /* O8: all folds 1..harm_max.  s has (log2(harm_max)+1) * nbins doubles,
  * fold l at s + l*nbins. */

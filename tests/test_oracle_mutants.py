@@ -12,6 +12,7 @@ from tests import test_oracle_pins as PINS
 from tests import test_oracle_distill as DS
 from tests import test_oracle_ell as ELL
 from tests import test_oracle_series_whitening as SW
+from tests import test_oracle_zap as ZP
 
 MUTANTS = {
     "kepler_step_sign": ("E -= step;", "E += step;"),
@@ -57,6 +58,11 @@ MUTANTS = {
     "appb_C0_dropped": ("    for (int k = 0; k <= 7; ++k) {\n        cosE", "    for (int k = 1; k <= 7; ++k) {\n        cosE"),
     "appb_sin_cos_swapped": ("sinE_b += S[k] * sin((double)k * M);", "sinE_b += S[k] * cos((double)k * M);"),
     "series_no_zero_offset": ("double d0 = tbo_roemer_delay_series(t, 0.0);", "double d0 = 0.0;"),
+    "zap_floor_low_end": ("double lo = ceil(lo_hz[i] * T), hi = floor(hi_hz[i] * T);",
+                          "double lo = floor(lo_hz[i] * T), hi = floor(hi_hz[i] * T);"),
+    "zap_open_high_end": ("if ((double)k >= lo && (double)k <= hi) phat[k] = 0.0;",
+                          "if ((double)k >= lo && (double)k < hi) phat[k] = 0.0;"),
+    "zap_not_applied": ("    tbo_zap(w->phat, nb, (double)n * c->tsamp, c->zap_lo_hz, c->zap_hi_hz, c->nzap);\n", ""),
     "fold_pick_index": ("for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * hp)];",
                         "for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * h)];"),
 }
@@ -83,6 +89,8 @@ def _pins():
     out.append(lambda: ELL.test_appendix_b_coefficients_are_the_bessel_taylor_polynomials(None, 0.3))
     out.append(lambda: ELL.test_series_delay_within_truncation_of_exact(None, 0.1))
     for f in [ELL.test_zero_eccentricity_is_the_circular_bt_delay, ELL.test_series_indices_follow_the_exact_delay]:
+        out.append(lambda f=f: f(None))
+    for f in [ZP.test_zapped_bins_are_zero_and_the_rest_untouched, ZP.test_zap_function_edges]:
         out.append(lambda f=f: f(None))
     for f in [DS.test_hand_worked_example, DS.test_tolerance_is_measured_at_the_ratio,
               DS.test_relative_tolerance_scales_with_the_target, DS.test_same_frequency_only]:
