@@ -132,6 +132,20 @@ tb_status tb_destroy(tb_plan_t plan);
 tb_status tb_load_series(tb_plan_t plan, const float* data, uint64_t n, double tsamp_s,
                          uint32_t flags, int32_t* series_id);
 
+/* Birdie zapping (App. A and Sec. 5.2 name Fourier birdie zapping among the
+ * per-series steps): replaces the series' list of interference intervals.
+ * For every template searched on the series afterwards, the whitened power of
+ * each bin k with lo_hz[i] <= k / T <= hi_hz[i] (T = n tsamp; bins
+ * ceil(lo T) .. floor(hi T) within 1 .. n/2) is 0 before the harmonic sum.
+ * count = 0 clears the list; at most TB_ZAP_MAX intervals; empty intervals
+ * (lo > hi) are ignored.  Waits for the plan's queued work first.  The raw
+ * powers and medians that tb_inspect_template reports are not affected.
+ * TB_ERR_INVALID_ARG for NULL arrays with count > 0, non-finite ends or too
+ * many intervals; TB_ERR_UNKNOWN_ID for an unknown series. */
+enum { TB_ZAP_MAX = 65536 };
+tb_status tb_zap_series(tb_plan_t plan, int32_t series_id, const double* lo_hz, const double* hi_hz,
+                        uint32_t count);
+
 /* Frees a series; requests already submitted on it complete first. */
 tb_status tb_unload_series(tb_plan_t plan, int32_t series_id);
 

@@ -29,6 +29,7 @@ TB_MEM_HOST = 0
 TB_MEM_DEVICE = 1
 TB_SERIES_WHITENING = 2  # OR into the load flags: whiten once from the series' own spectrum
 TB_DELAY_SERIES = 1  # tb_config.flags: Roemer delay from the App. B series (ELL7) instead of BT-Newton
+TB_ZAP_MAX = 65536  # most birdie intervals per series
 
 
 class TbConfig(C.Structure):
@@ -82,7 +83,7 @@ EXPORTS = [
     "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
-    "tb_set_budget", "tb_distill",
+    "tb_set_budget", "tb_distill", "tb_zap_series",
 ]
 
 
@@ -130,6 +131,7 @@ def _load():
     L.tb_memory.argtypes = [vp, P(u64), P(u64)]
     L.tb_set_budget.argtypes = [vp, u64]
     L.tb_distill.argtypes = [vp, u64, u32, u32, u32, vp, vp, P(u64)]
+    L.tb_zap_series.argtypes = [vp, i32, vp, vp, u32]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tb_default_config", "tb_strerror"):
@@ -270,6 +272,14 @@ def tb_profile_read(plan: int):
     return ms, ln, int(t.value)
 
 
+def tb_zap_series(plan: int, series_id: int, intervals) -> None:
+    """intervals: (lo_hz, hi_hz) pairs whose bins are zeroed after whitening
+    for every later search on the series; empty clears the list."""
+    z = np.ascontiguousarray(np.asarray(intervals, dtype=np.float64).reshape(-1, 2).T)
+    lo, hi = np.ascontiguousarray(z[0]), np.ascontiguousarray(z[1])
+    _check(_L.tb_zap_series(C.c_void_p(plan), int(series_id), _ptr(lo), _ptr(hi), lo.size), "tb_zap_series")
+
+
 def tb_distill(cands, max_ratio: int = 16, tol: int = 16, ppm: int = 0):
     """Candidate grouping on the host: (kept candidates in strength order,
     group sizes).  tol: sixteenths of a fundamental bin; ppm: parts per
@@ -355,6 +365,10 @@ class Plan:
         sid = tb_load_series(self.handle, data, tsamp, n=n, flags=flags)
         self.series_n[sid] = int(n if (flags & TB_MEM_DEVICE) else np.asarray(data).size)
         return sid
+
+    def zap(self, sid, intervals):
+        """Birdie intervals (lo_hz, hi_hz) for the series; [] clears them."""
+        tb_zap_series(self.handle, sid, intervals)
 
     def unload_series(self, sid):
         tb_unload_series(self.handle, sid)

@@ -112,6 +112,9 @@ struct SeriesRec {
     size_t bytes = 0;     // everything the series holds
     float* fac = nullptr; // whitened once: factors ln2 / m(k), M + 1 floats; nullptr = per template
     float* med = nullptr; // and the series' block medians (same allocation)
+    int2* zap = nullptr;  // birdie bin ranges [x, y], sorted and disjoint (own allocation)
+    int nzap = 0;
+    size_t zap_bytes = 0;
 };
 
 struct GeoRec {
@@ -477,7 +480,8 @@ tb_status enqueue(tb_plan_t p, const Crew& crew, const SeriesRec& sr, Geometry* 
             marks = &p->prof_events.back();
             p->prof_templates += (uint64_t)nslots;
         }
-        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, sr.fac, pp, ring, counter, ins, stream,
+        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, *ws, sr.fac, sr.zap, sr.nzap, pp, ring, counter,
+                        ins, stream,
                         marks) !=
             hipSuccess)
             return TB_ERR_DEVICE;
@@ -661,7 +665,10 @@ tb_status tb_destroy(tb_plan_t p)
         sync_lanes(p);
         for (auto& kv : p->reqs) free_request(p, kv.second);
         sync_lanes(p);
-        for (auto& kv : p->series) hipFree(kv.second.d);
+        for (auto& kv : p->series) {
+            hipFree(kv.second.d);
+            hipFree(kv.second.zap);
+        }
         for (auto& L : p->lanes)
             for (auto& kv : L.slots) free_slots(kv.second.s);
         for (auto& kv : p->geo) free_geometry(kv.second);
@@ -757,8 +764,67 @@ tb_status tb_unload_series(tb_plan_t p, int32_t id)
     TB_TRY(hipSetDevice(p->cfg.device));
     TB_TRY(sync_lanes(p));
     hipFree(it->second.d);
-    p->held -= it->second.bytes;
+    hipFree(it->second.zap);
+    p->held -= it->second.bytes + it->second.zap_bytes;
     p->series.erase(it);
+    return TB_OK;
+}
+
+tb_status tb_zap_series(tb_plan_t p, int32_t sid, const double* lo_hz, const double* hi_hz, uint32_t count)
+{
+    if (!p || (count && (!lo_hz || !hi_hz)) || count > TB_ZAP_MAX) return TB_ERR_INVALID_ARG;
+    for (uint32_t i = 0; i < count; ++i)
+        if (!std::isfinite(lo_hz[i]) || !std::isfinite(hi_hz[i])) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto it = p->series.find(sid);
+    if (it == p->series.end()) return TB_ERR_UNKNOWN_ID;
+    SeriesRec& sr = it->second;
+    // bins k with lo <= k / T <= hi, 1 <= k <= M; merged into disjoint ranges
+    const double T = (double)sr.n * sr.tsamp;
+    const int64_t M = sr.n / 2;
+    std::vector<std::pair<int64_t, int64_t>> r;
+    for (uint32_t i = 0; i < count; ++i) {
+        const double lo = std::ceil(lo_hz[i] * T), hi = std::floor(hi_hz[i] * T);
+        const int64_t a = lo < 1.0 ? 1 : (lo > (double)M ? M + 1 : (int64_t)lo);
+        const int64_t b = hi > (double)M ? M : (hi < 0.0 ? 0 : (int64_t)hi);
+        if (a <= b) r.emplace_back(a, b);
+    }
+    std::sort(r.begin(), r.end());
+    std::vector<int2> merged;
+    for (const auto& ab : r) {
+        if (!merged.empty() && ab.first <= (int64_t)merged.back().y + 1)
+            merged.back().y = (int)std::max<int64_t>(merged.back().y, ab.second);
+        else
+            merged.push_back(make_int2((int)ab.first, (int)ab.second));
+    }
+    TB_TRY(hipSetDevice(p->cfg.device));
+    TB_TRY(sync_lanes(p));
+    Geometry* g = nullptr;
+    tb_status st = get_geometry(p, ilog2((uint64_t)sr.n), &g);
+    if (st) return st;
+    int2* dz = nullptr;
+    const size_t bytes = sizeof(int2) * merged.size();
+    if (bytes) {
+        if ((st = reserve(p, bytes))) return st;
+        if (hipMalloc(&dz, bytes) != hipSuccess) {
+            p->held -= bytes;
+            return TB_ERR_OOM;
+        }
+        if (hipMemcpy(dz, merged.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            hipFree(dz);
+            p->held -= bytes;
+            return TB_ERR_DEVICE;
+        }
+    }
+    hipFree(sr.zap);
+    p->held -= sr.zap_bytes;
+    sr.zap = dz;
+    sr.nzap = (int)merged.size();
+    sr.zap_bytes = bytes;
+    // a series whitened once carries the ranges in its factors
+    if (sr.fac && (launch_series_factors(*g, sr.med, sr.fac, sr.zap, sr.nzap, p->stream) != hipSuccess ||
+                   hipStreamSynchronize(p->stream) != hipSuccess))
+        return TB_ERR_DEVICE;
     return TB_OK;
 }
 
@@ -1109,7 +1175,8 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
         // so the raw power comes from a pass without the factors
         Inspect raw;
         raw.power = ins.power;
-        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, 0, 1, *ws, nullptr, pp, ring, counter, raw, p->stream) !=
+        if (launch_wave(*g, sr.d, sr.tsamp, d_tm, 0, 1, *ws, nullptr, nullptr, 0, pp, ring, counter, raw,
+                        p->stream) !=
             hipSuccess)
             st = TB_ERR_DEVICE;
         ins.power = nullptr;

@@ -131,16 +131,21 @@ using Marks = std::vector<std::pair<int, hipEvent_t>>;
 // groups of ws.BY, so that a group's exchange buffer is still cached when
 // pass 2 reads it).  fac: whitening factors of a series whitened once (M + 1
 // floats), applied by pass 2 in place of the per-template medians and
-// whitening; nullptr for per-template whitening.  With marks, an event is
-// recorded before every kernel.
+// whitening; nullptr for per-template whitening.  zap[0..nzap): the series'
+// birdie bin ranges (inclusive, sorted, disjoint), zeroed by the per-template
+// whitening (a series whitened once carries them in fac).  With marks, an
+// event is recorded before every kernel.
 hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
-                       int nslots, const Slots& ws, const float* fac, const PeakParams& pp, uint4* ring,
-                       uint32_t* counter, const Inspect& ins, hipStream_t s, Marks* marks = nullptr);
+                       int nslots, const Slots& ws, const float* fac, const int2* zap, int nzap, const PeakParams& pp,
+                       uint4* ring, uint32_t* counter, const Inspect& ins, hipStream_t s, Marks* marks = nullptr);
 // The power spectrum of the series x read through template tm (one without
 // orbit reads it as loaded), its block medians into med (nblk floats) and the
 // whitening factors ln2 / m(k) into fac (M + 1 floats).  Uses slot 0 of ws.
 hipError_t launch_series_levels(const Geometry& g, const float* x, double tsamp, const TmplDev* tm,
                                 const Slots& ws, float* med, float* fac, hipStream_t s);
+// Factors ln2 / m(k) from the series medians, then 0 over the birdie ranges.
+hipError_t launch_series_factors(const Geometry& g, const float* med, float* fac, const int2* zap, int nzap,
+                                 hipStream_t s);
 hipError_t launch_copy(float4* dst, const float4* src, size_t count, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
 // Rewrites a mean-removed series into the tile order pass 1 reads.

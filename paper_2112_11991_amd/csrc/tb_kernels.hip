@@ -904,21 +904,57 @@ __device__ __forceinline__ WhitenLine whiten_line(const float* __restrict__ md, 
 
 constexpr float LN2F = 0.69314718055994530942f;
 
-// Per template, in place.
+// First of the sorted, disjoint bin ranges zap[0..nzap) that ends at or
+// after bin q (nzap if none).
+__device__ __forceinline__ int first_zap(const int2* __restrict__ zap, int nzap, int q)
+{
+    int lo = 0, hi = nzap;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (zap[mid].y < q) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Per template, in place.  Bins inside one of the series' birdie ranges
+// (inclusive [x, y], sorted and disjoint) are set to 0; each thread's bins
+// ascend, so its range pointer only moves forward.
 __global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_stride, int64_t M, int W, int nblk,
-                                               const float* __restrict__ med, size_t med_stride)
+                                               const float* __restrict__ med, size_t med_stride,
+                                               const int2* __restrict__ zap, int nzap)
 {
     const int b = blockIdx.x;
     float* Ps = P + blockIdx.y * p_stride;
     const WhitenLine L = whiten_line(med + blockIdx.y * med_stride, b, (int)M, W, nblk);
+    if (nzap == 0) {
 #pragma unroll 4
-    for (int i = threadIdx.x; i < L.cnt; i += NT) {
-        const int q = L.start + i;
-        const float level = L.level(q);
-        const float p = Ps[q];
-        Ps[q] = level > 0.0f ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
+        for (int i = threadIdx.x; i < L.cnt; i += NT) {
+            const int q = L.start + i;
+            const float level = L.level(q);
+            const float p = Ps[q];
+            Ps[q] = level > 0.0f ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
+        }
+    } else {
+        int r = first_zap(zap, nzap, L.start);
+        for (int i = threadIdx.x; i < L.cnt; i += NT) {
+            const int q = L.start + i;
+            while (r < nzap && zap[r].y < q) ++r;
+            const bool zapped = r < nzap && zap[r].x <= q;
+            const float level = L.level(q);
+            const float p = Ps[q];
+            Ps[q] = (level > 0.0f && !zapped) ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
+        }
     }
     if (b == 0 && threadIdx.x == 0) Ps[0] = 0.0f;
+}
+
+// Zeroes the bins of the birdie ranges in a series' whitening factors; one
+// workgroup per range.
+__global__ __launch_bounds__(NT) void k_zap_factors(float* __restrict__ fac, const int2* __restrict__ zap)
+{
+    const int2 z = zap[blockIdx.x];
+    for (int q = z.x + (int)threadIdx.x; q <= z.y; q += NT) fac[q] = 0.0f;
 }
 
 // Once per series: the factor ln2 / m(k) (0 where m(k) <= 0, and at k = 0)
@@ -1231,13 +1267,20 @@ hipError_t launch_series_levels(const Geometry& g, const float* x, double tsamp,
     hipError_t e;
     if ((e = launch_power(g, x, tsamp, tm, 1, ws, nullptr, nullptr, s, nullptr)) != hipSuccess) return e;
     if ((e = launch_median(g, 1, ws, med, 0, s)) != hipSuccess) return e;
+    return launch_series_factors(g, med, fac, nullptr, 0, s);
+}
+
+hipError_t launch_series_factors(const Geometry& g, const float* med, float* fac, const int2* zap, int nzap,
+                                 hipStream_t s)
+{
     hipLaunchKernelGGL(k_series_factor, dim3(g.nblk), dim3(NT), 0, s, med, g.M, g.W, g.nblk, fac);
+    if (nzap) hipLaunchKernelGGL(k_zap_factors, dim3(nzap), dim3(NT), 0, s, fac, zap);
     return hipGetLastError();
 }
 
 hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const TmplDev* tm, int tmpl_base,
-                       int nslots, const Slots& ws, const float* fac, const PeakParams& pp, uint4* ring,
-                       uint32_t* counter, const Inspect& ins, hipStream_t s, Marks* marks)
+                       int nslots, const Slots& ws, const float* fac, const int2* zap, int nzap, const PeakParams& pp,
+                       uint4* ring, uint32_t* counter, const Inspect& ins, hipStream_t s, Marks* marks)
 {
     hipError_t e;
     if ((e = launch_power(g, x, tsamp, tm + tmpl_base, nslots, ws, fac, ins.src, s, marks)) != hipSuccess) return e;
@@ -1250,7 +1293,7 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
         if ((e = launch_median(g, nslots, ws, ws.med, ws.med_stride, s)) != hipSuccess) return e;
         if ((e = mark(marks, K_WHITEN, s)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk,
-                           ws.med, ws.med_stride);
+                           ws.med, ws.med_stride, zap, nzap);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(marks, K_HARMSUM, s)) != hipSuccess) return e;
