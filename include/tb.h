@@ -225,6 +225,32 @@ tb_status tb_profile_read(tb_plan_t plan, double ms[6], uint64_t launches[6], ui
  * copy.  A measurement utility: the practical HBM ceiling. */
 tb_status tb_stream_copy(tb_plan_t plan, void* dst, const void* src, uint64_t bytes, uint32_t reps, double* ms);
 
+/* Random template bank (Secs. 2.3-2.7).  Proper-volume density of the bank
+ * at the given points: the square root of the determinant of the phase
+ * metric (Sec. 2.2: time averages of products of phase derivatives, minus the
+ * products of their averages) projected to constant spin frequency (Sec.
+ * 2.5), times (2 pi f_max T)^n (Sec. 2.6), per unit of the bank's coordinates
+ *   TB_BANK_CIRCULAR   (P_orb [s], tau [lt-s], alpha)            n = 3
+ *   TB_BANK_ELLIPTICAL (P_orb, tau, alpha, e, psi = omega_rad)   n = 5.
+ * The volume of a prior region is the integral of this density; the number
+ * of random templates for coverage eta and mismatch m is
+ * ln(1 - eta) / ln(1 - m^(n/2) C_n / V), C_n the unit n-ball volume, and the
+ * templates are drawn with probability proportional to it.  Averages use
+ * `nodes` Gauss-Legendre nodes over the observation (8..8192; 128 resolves
+ * up to about 10 orbits).  points and out are host arrays of count entries
+ * (templates must be valid: P_orb > 0, tau >= 0, 0 <= e < 1; e and psi are
+ * ignored for circular banks); *kernel_ms (may be NULL) receives the device
+ * time of the kernel.  FP64 throughout. */
+enum { TB_BANK_CIRCULAR = 0, TB_BANK_ELLIPTICAL = 1 };
+typedef struct {
+    uint32_t kind;    /* TB_BANK_CIRCULAR or TB_BANK_ELLIPTICAL */
+    uint32_t nodes;   /* quadrature nodes over the observation */
+    double tobs_s;    /* observation time T */
+    double fmax_hz;   /* highest spin frequency the bank is built for */
+} tb_bank_metric;
+tb_status tb_bank_density(tb_plan_t plan, const tb_bank_metric* m, const tb_template* points, uint64_t count,
+                          double* out, double* kernel_ms);
+
 /* Candidate grouping (App. A: the search software groups repeated detections
  * of the same signal and keeps the strongest; the paper gives no rule, this
  * is the library's).  Host arrays, no plan or device needed.

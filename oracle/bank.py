@@ -72,6 +72,16 @@ def _derivatives(kind, T, porb, tau, alpha, ecc, psi, u):
 def sqrt_det_gamma(kind, T, f_max, porb, tau, alpha, ecc=None, psi=None, nodes: int = 256):
     """sqrt(det gamma) chi^n in the dimensionless coordinates (see module
     docstring); kind 0 circular (n = 3), 1 elliptical (n = 5)."""
+    gam = gamma_tilde(kind, T, porb, tau, alpha, ecc, psi, nodes)
+    n = gam.shape[1]
+    det = np.linalg.det(gam)
+    chi = 2.0 * np.pi * f_max * T
+    return np.sqrt(np.clip(det, 0.0, None)) * chi ** n
+
+
+def gamma_tilde(kind, T, porb, tau, alpha, ecc=None, psi=None, nodes: int = 256):
+    """The frequency-projected metric of the dimensionless phase, one n x n
+    matrix per point."""
     porb = np.atleast_1d(np.asarray(porb, dtype=np.float64))
     tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), porb.shape)
     alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), porb.shape)
@@ -81,15 +91,15 @@ def sqrt_det_gamma(kind, T, f_max, porb, tau, alpha, ecc=None, psi=None, nodes: 
     x, w = np.polynomial.legendre.leggauss(nodes)
     u, w = 0.5 * (x + 1.0), 0.5 * w
     d = _derivatives(kind, T, porb, tau, alpha, ecc, psi, u)
-    mean = d @ w                                            # <d_a>
-    g = np.einsum("pan,pbn,n->pab", d, d, w) - mean[:, :, None] * mean[:, None, :]
-    gk = np.einsum("pan,n->pa", d, u * w) - mean * (u @ w)  # g_{kappa a}
-    gkk = (u * u) @ w - (u @ w) ** 2
-    gam = g - gk[:, :, None] * gk[:, None, :] / gkk
-    n = gam.shape[1]
-    det = np.linalg.det(gam)
-    chi = 2.0 * np.pi * f_max * T
-    return np.sqrt(np.clip(det, 0.0, None)) * chi ** n
+    # g_ab - g_ka g_kb / g_kk with g_ab = <ab> - <a><b> and d_kappa Phi~ = u is
+    # the average product of the residuals r_a of the derivatives after a
+    # weighted least-squares fit of 1 and u (the same quantity, computed without
+    # subtracting nearly equal terms when the orbital arc is short)
+    dc = d - (d @ w)[:, :, None]
+    uc = u - u @ w
+    slope = np.einsum("pan,n->pa", dc, uc * w) / ((uc * uc) @ w)
+    r = dc - slope[:, :, None] * uc[None, None, :]
+    return np.einsum("pan,pbn,n->pab", r, r, w)
 
 
 def density(kind, T, f_max, porb, tau, alpha, ecc=None, psi=None, nodes: int = 256):

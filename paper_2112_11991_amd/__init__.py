@@ -30,6 +30,8 @@ TB_MEM_DEVICE = 1
 TB_SERIES_WHITENING = 2  # OR into the load flags: whiten once from the series' own spectrum
 TB_DELAY_SERIES = 1  # tb_config.flags: Roemer delay from the App. B series (ELL7) instead of BT-Newton
 TB_ZAP_MAX = 65536  # most birdie intervals per series
+TB_BANK_CIRCULAR = 0  # bank coordinates (P_orb, tau, alpha)
+TB_BANK_ELLIPTICAL = 1  # (P_orb, tau, alpha, e, psi)
 
 
 class TbConfig(C.Structure):
@@ -83,8 +85,12 @@ EXPORTS = [
     "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
-    "tb_set_budget", "tb_distill", "tb_zap_series",
+    "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density",
 ]
+
+
+class TbBankMetric(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("nodes", C.c_uint32), ("tobs_s", C.c_double), ("fmax_hz", C.c_double)]
 
 
 class TbError(RuntimeError):
@@ -132,6 +138,7 @@ def _load():
     L.tb_set_budget.argtypes = [vp, u64]
     L.tb_distill.argtypes = [vp, u64, u32, u32, u32, vp, vp, P(u64)]
     L.tb_zap_series.argtypes = [vp, i32, vp, vp, u32]
+    L.tb_bank_density.argtypes = [vp, P(TbBankMetric), vp, u64, vp, P(C.c_double)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tb_default_config", "tb_strerror"):
@@ -272,6 +279,18 @@ def tb_profile_read(plan: int):
     return ms, ln, int(t.value)
 
 
+def tb_bank_density(plan: int, kind: int, tobs_s: float, fmax_hz: float, points, nodes: int = 128):
+    """Proper-volume density of the random template bank at the points
+    (TEMPLATE_DTYPE array): (densities, kernel milliseconds)."""
+    pts = np.ascontiguousarray(points, dtype=TEMPLATE_DTYPE)
+    out = np.zeros(max(1, pts.size), dtype=np.float64)
+    ms = C.c_double(0.0)
+    m = TbBankMetric(int(kind), int(nodes), float(tobs_s), float(fmax_hz))
+    _check(_L.tb_bank_density(C.c_void_p(plan), C.byref(m), _ptr(pts), pts.size, _ptr(out), C.byref(ms)),
+           "tb_bank_density")
+    return out[: pts.size], ms.value
+
+
 def tb_zap_series(plan: int, series_id: int, intervals) -> None:
     """intervals: (lo_hz, hi_hz) pairs whose bins are zeroed after whitening
     for every later search on the series; empty clears the list."""
@@ -365,6 +384,9 @@ class Plan:
         sid = tb_load_series(self.handle, data, tsamp, n=n, flags=flags)
         self.series_n[sid] = int(n if (flags & TB_MEM_DEVICE) else np.asarray(data).size)
         return sid
+
+    def bank_density(self, kind, tobs_s, fmax_hz, points, nodes=128):
+        return tb_bank_density(self.handle, kind, tobs_s, fmax_hz, points, nodes)
 
     def zap(self, sid, intervals):
         """Birdie intervals (lo_hz, hi_hz) for the series; [] clears them."""

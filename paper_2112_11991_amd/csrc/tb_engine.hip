@@ -770,6 +770,37 @@ tb_status tb_unload_series(tb_plan_t p, int32_t id)
     return TB_OK;
 }
 
+tb_status tb_bank_density(tb_plan_t p, const tb_bank_metric* m, const tb_template* pts, uint64_t count,
+                          double* out, double* kernel_ms)
+{
+    if (!p || !m || (count && (!pts || !out)) || count > (1ull << 31) || (m->kind != TB_BANK_CIRCULAR &&
+        m->kind != TB_BANK_ELLIPTICAL) || m->nodes < 8 || m->nodes > 8192 || !(m->tobs_s > 0.0) ||
+        !std::isfinite(m->tobs_s) || !(m->fmax_hz > 0.0) || !std::isfinite(m->fmax_hz))
+        return TB_ERR_INVALID_ARG;
+    for (uint64_t i = 0; i < count; ++i) {
+        const tb_template& t = pts[i];
+        if (!valid_template(t)) return TB_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lk(p->mu);
+    TB_TRY(hipSetDevice(p->cfg.device));
+    if (kernel_ms) *kernel_ms = 0.0;
+    if (count == 0) return TB_OK;
+    tb_template* d_pts = nullptr;
+    double* d_out = nullptr;
+    const size_t bp = sizeof(tb_template) * count, bo = sizeof(double) * count;
+    tb_status st = TB_OK;
+    if (hipMalloc(&d_pts, bp) != hipSuccess || hipMalloc(&d_out, bo) != hipSuccess) st = TB_ERR_OOM;
+    if (!st && (hipMemcpyAsync(d_pts, pts, bp, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                launch_bank_density((int)m->kind, (int)m->nodes, m->tobs_s, m->fmax_hz, d_pts, (uint32_t)count, d_out,
+                                    p->stream, kernel_ms) != hipSuccess ||
+                hipMemcpy(out, d_out, bo, hipMemcpyDeviceToHost) != hipSuccess))
+        st = TB_ERR_DEVICE;
+    hipStreamSynchronize(p->stream);
+    hipFree(d_pts);
+    hipFree(d_out);
+    return st;
+}
+
 tb_status tb_zap_series(tb_plan_t p, int32_t sid, const double* lo_hz, const double* hi_hz, uint32_t count)
 {
     if (!p || (count && (!lo_hz || !hi_hz)) || count > TB_ZAP_MAX) return TB_ERR_INVALID_ARG;

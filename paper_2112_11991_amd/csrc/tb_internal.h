@@ -151,5 +151,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s)
 // Rewrites a mean-removed series into the tile order pass 1 reads.
 hipError_t launch_tile_series(const Geometry& g, const float* in, float* out, hipStream_t s);
 int harmsum_tile();
+// Bank density of count points (device arrays); kind 0 circular, 1 elliptical;
+// waits for the stream; *ms (may be null) receives the kernel time.
+hipError_t launch_bank_density(int kind, int nodes, double T, double fmax, const tb_template* d_pts, uint32_t count,
+                               double* d_out, hipStream_t s, double* ms);
 
 }  // namespace tb

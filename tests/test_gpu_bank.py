@@ -1,0 +1,107 @@
+"""The random-template-bank density kernel (tb_bank_density) against the
+oracle, the paper's circular bank size through the library's generator, and
+the generator's selection against the oracle's rejection step."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import bank as obank
+
+pytestmark = pytest.mark.gpu
+HOUR = 3600.0
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tb():
+    import paper_2112_11991_amd as tb
+
+    return tb
+
+
+def _points(tb, kind, rng, count, orbits=(0.05, 12.0), T=1.2 * HOUR):
+    a = np.zeros(count, dtype=tb.TEMPLATE_DTYPE)
+    a["porb_s"] = T / rng.uniform(orbits[0], orbits[1], count)
+    a["tau_lts"] = rng.uniform(0.0, 10.0, count)
+    a["alpha_rad"] = rng.uniform(0.0, 2 * math.pi, count)
+    if kind == 1:
+        a["ecc"] = rng.uniform(0.005, 0.5, count)
+        a["omega_rad"] = rng.uniform(0.0, 2 * math.pi, count)
+    return a
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_density_matches_oracle(tb, kind):
+    """Relative agreement within the conditioning of each point's projected
+    metric: |d_gpu / d_or - 1| <= 1e-11 + 20 n kappa eps, kappa the condition
+    number of the metric scaled to unit diagonal (an FP64 determinant of a
+    symmetric matrix is good to about kappa eps relative, its square root to
+    half that).  Points with kappa > 1e12 (below a tenth of an orbit the
+    elliptical directions are nearly dependent) are not determined to better
+    than ~1e-4 in FP64 and are only counted."""
+    T, f = 1.2 * HOUR, 66.67
+    rng = np.random.default_rng(40 + kind)
+    pts = _points(tb, kind, rng, 2000, T=T)
+    with tb.Plan() as plan:
+        dg, ms = plan.bank_density(kind, T, f, pts, nodes=128)
+    ecc = pts["ecc"] if kind else None
+    psi = pts["omega_rad"] if kind else None
+    do = obank.density(kind, T, f, pts["porb_s"], pts["tau_lts"], pts["alpha_rad"], ecc, psi, nodes=128)
+    gam = obank.gamma_tilde(kind, T, pts["porb_s"], pts["tau_lts"], pts["alpha_rad"], ecc, psi, nodes=128)
+    dia = np.sqrt(np.einsum("pii->pi", gam))
+    kappa = np.linalg.cond(gam / dia[:, :, None] / dia[:, None, :])
+    n = 3 if kind == 0 else 5
+    ok = kappa <= 1e12
+    tol = 1e-11 + 20 * n * kappa[ok] * np.finfo(np.float64).eps
+    rel = np.abs(dg[ok] / do[ok] - 1.0)
+    _say("kind %d: max rel %.3g, max kappa %.3g, %d ill-determined, kernel %.3f ms for %d points" % (
+        kind, rel.max(), kappa[ok].max(), int((~ok).sum()), ms, pts.size))
+    assert np.all(rel <= tol), (rel / tol).max()
+    assert np.all(do[ok] > 0) and ok.mean() > 0.98
+
+
+def test_circular_bank_size_of_the_paper(tb):
+    """The library's generator on the Table 1 priors (e = 0): the count agrees
+    with the paper's 10,128 within 3 standard errors of its 2^18-point
+    volume; the drawn bank has that many templates inside the prior region."""
+    from paper_2112_11991_amd import bank
+
+    pr = bank.Priors(porb_s=(6 * HOUR, 12 * HOUR), m_pulsar_min=1.4, m_comp_max=8.0)
+    rng = np.random.default_rng(2112)
+    with tb.Plan() as plan:
+        tm, info = bank.generate(plan, tb.TB_BANK_CIRCULAR, 1.2 * HOUR, 66.67, pr, 0.9, 0.2, rng)
+    _say("circular bank: %s" % info)
+    assert abs(info["count"] - 10128) <= 3 * info["volume_err"] / info["volume"] * info["count"] + 1
+    assert tm.size == info["count"]
+    lim = bank.kepler_tau_limit(tm["porb_s"], 1.4, 8.0)
+    assert np.all((tm["porb_s"] >= 6 * HOUR) & (tm["porb_s"] <= 12 * HOUR) & (tm["tau_lts"] <= lim))
+    assert info["above_scale"] < 1e-3 * info["proposals"]
+
+
+def test_selection_matches_the_oracle(tb):
+    """Same proposals, uniforms and acceptance scale: the points the GPU
+    densities keep are the oracle's, except where u * wmax is within the
+    densities' agreement of w."""
+    T, f = 1.2 * HOUR, 66.67
+    rng = np.random.default_rng(9)
+    pts, q = obank.proposals(1, rng, 4000, (6 * HOUR, 12 * HOUR), 1.4, 8.0, ecc_max=0.1)
+    a = np.zeros(4000, dtype=tb.TEMPLATE_DTYPE)
+    a["porb_s"], a["tau_lts"], a["alpha_rad"], a["ecc"], a["omega_rad"] = (pts["porb"], pts["tau"], pts["alpha"],
+                                                                           pts["ecc"], pts["psi"])
+    with tb.Plan() as plan:
+        dg, _ = plan.bank_density(1, T, f, a)
+    do = obank.density(1, T, f, pts["porb"], pts["tau"], pts["alpha"], pts["ecc"], pts["psi"], nodes=128)
+    u = rng.uniform(0, 1, 4000)
+    wmax = float(np.quantile(do / q, 0.9))  # the density is peaked (it grows as e^2): a scale that keeps hundreds
+    kg = set(obank.select(dg, q, u, wmax).tolist())
+    ko = set(obank.select(do, q, u, wmax).tolist())
+    edge = np.abs(u * wmax - do / q) <= 1e-6 * do / q
+    assert len(ko) > 100
+    assert all(edge[i] for i in kg ^ ko)

@@ -46,12 +46,19 @@ def test_circular_bank_size_of_the_paper(oracle_lib):
 
 def test_eccentric_metric_degenerates_at_zero_eccentricity(oracle_lib):
     """At e = 0, d/d alpha = Y d/dX - X d/dY: the elliptical metric is singular
-    and its density grows from zero with e."""
-    T, f = 1.2 * HOUR, 66.67
-    args = (T, f, 8 * HOUR, 4.0, 0.4)
-    d = [bank.sqrt_det_gamma(1, *args, ecc=e, psi=1.1)[0] for e in (0.0, 0.01, 0.02, 0.05, 0.1)]
-    assert d[0] < 1e-6 * d[1]
-    assert d[1] < d[2] < d[3] < d[4]
+    (smallest eigenvalue of the unit-diagonal metric at rounding level), and
+    since eccentricity separates the directions at first order in e, that
+    eigenvalue grows as e^2; the density grows with e."""
+    T = 1.2 * HOUR
+    lam = {}
+    for e in (0.0, 0.001, 0.01, 0.02):
+        g = bank.gamma_tilde(1, T, 8 * HOUR, 4.0, 0.4, ecc=e, psi=1.1)[0]
+        d = np.sqrt(np.diag(g))
+        lam[e] = np.linalg.eigvalsh(g / np.outer(d, d))[0]
+    assert lam[0.0] < 1e-14
+    assert abs(lam[0.01] / lam[0.001] / 100 - 1) < 0.05 and abs(lam[0.02] / lam[0.01] / 4 - 1) < 0.05
+    dens = [bank.sqrt_det_gamma(1, T, 66.67, 8 * HOUR, 4.0, 0.4, ecc=e, psi=1.1)[0] for e in (0.01, 0.02, 0.05, 0.1)]
+    assert dens[0] < dens[1] < dens[2] < dens[3]
 
 
 def test_volume_does_not_depend_on_the_sampling_coordinates(oracle_lib):
