@@ -172,6 +172,40 @@ def grouping_report(tb, cands, with_oracle: bool):
     return rep
 
 
+def bank_report(tb, with_oracle: bool):
+    """Random-template-bank density kernel on the Table 1 prior region
+    (T = 1.2 h, f_max = 66.67 Hz, P_orb 6-12 h, 1.4 + 8 solar masses; e < 0.1
+    for the elliptical bank): points per second of device time, 128 nodes;
+    the oracle's FP64 numpy density timed beside it on a sample."""
+    from paper_2112_11991_amd import bank
+
+    T, f = 1.2 * 3600.0, 66.67
+    out = {"unit": "points/s", "nodes": 128}
+    rng = np.random.default_rng(2112)
+    with tb.Plan() as plan:
+        for name, kind, count, emax in (("circular", tb.TB_BANK_CIRCULAR, 1 << 20, 0.0),
+                                        ("elliptical", tb.TB_BANK_ELLIPTICAL, 1 << 18, 0.1)):
+            pr = bank.Priors(porb_s=(6 * 3600.0, 12 * 3600.0), ecc_max=emax)
+            pts, _ = bank._draw(kind, pr, rng, count)
+            plan.bank_density(kind, T, f, pts[:4096])
+            _, ms = plan.bank_density(kind, T, f, pts)
+            rec = {"points": count, "kernel_ms": ms, "value": count / (ms * 1e-3)}
+            if with_oracle:
+                from oracle import bank as obank
+
+                k = 2000
+                t0 = time.perf_counter()
+                obank.density(kind, T, f, pts["porb_s"][:k], pts["tau_lts"][:k], pts["alpha_rad"][:k],
+                              pts["ecc"][:k] if kind else None, pts["omega_rad"][:k] if kind else None, nodes=128)
+                rec["oracle"] = {"value": k / (time.perf_counter() - t0), "sample": k, "cores": 1}
+            out[name] = rec
+        pr = bank.Priors(porb_s=(6 * 3600.0, 12 * 3600.0))
+        V, err, _ = bank.volume(plan, tb.TB_BANK_CIRCULAR, T, f, pr, rng, points=1 << 20)
+        out["table1_circular_count"] = {"value": bank.template_count(V, 3, 0.9, 0.2), "rel_err": err / V,
+                                        "paper": 10128}
+    return out
+
+
 def stream_copy_gbs(plan, tb):
     import torch
 
@@ -281,6 +315,8 @@ def run_bank(args, tb, torch):
     plan.close()
     out["grouping"] = grouping_report(tb, np.concatenate(last) if last else np.zeros(0, tb.CANDIDATE_DTYPE),
                                       not args.no_cpu_baseline)
+    if args.workload == "c2":
+        out["bank"] = bank_report(tb, not args.no_cpu_baseline)
     if args.workload == "c4" and not args.no_plain:
         idx = list(range(min(4, len(w.series))))
         rates = plain_vs_batched(tb, w, idx, 256)
