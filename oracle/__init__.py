@@ -170,6 +170,11 @@ def _bind(L):
         C.c_void_p, C.c_int64, P(C.c_int64),
     ]
     L.tbo_search.restype = C.c_int
+    L.tbo_dispersion_constant.argtypes = []
+    L.tbo_dispersion_constant.restype = C.c_double
+    L.tbo_dedisperse.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_void_p,
+                                 C.c_int32, C.c_void_p]
+    L.tbo_dedisperse.restype = C.c_int64
     L.tbo_distill.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                               P(C.c_int64)]
     L.tbo_distill.restype = C.c_int
@@ -382,3 +387,22 @@ def distill(cands: np.ndarray, max_ratio: int = 16, tol: int = 16, ppm: int = 0)
                          C.byref(nk)) != 0:
         raise ValueError("tbo_distill: bad arguments")
     return out[: nk.value], grp[: nk.value]
+
+
+def dispersion_constant() -> float:
+    return lib().tbo_dispersion_constant()
+
+
+def dedisperse(data: np.ndarray, fch1_mhz: float, foff_mhz: float, tsamp: float, dms) -> np.ndarray:
+    """data: uint8 (nsamp, nchan), time-major.  Returns (ndm, nout) float32."""
+    data = np.ascontiguousarray(data, dtype=np.uint8)
+    nsamp, nchan = data.shape
+    dm = np.ascontiguousarray(dms, dtype=np.float64)
+    nout = lib().tbo_dedisperse(_ptr(data), nchan, nsamp, float(fch1_mhz), float(foff_mhz), float(tsamp), _ptr(dm),
+                                dm.size, None)
+    if nout < 1:
+        raise ValueError("tbo_dedisperse: bad arguments")
+    out = np.empty((dm.size, nout), dtype=np.float32)
+    lib().tbo_dedisperse(_ptr(data), nchan, nsamp, float(fch1_mhz), float(foff_mhz), float(tsamp), _ptr(dm), dm.size,
+                         _ptr(out))
+    return out

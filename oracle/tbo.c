@@ -738,3 +738,48 @@ int tbo_distill(const tbo_candidate* in, int64_t n, int32_t max_ratio, int64_t t
     free(absorbed);
     return 0;
 }
+
+/* ----------------------------------------------------------- O0 --------- */
+/* Cold-plasma dispersion: a pulse at frequency f arrives K_DM DM / f^2 later
+ * than at infinite frequency, K_DM = e^2 / (2 pi m_e c) in units of
+ * s MHz^2 pc^-1 cm^3 (the paper names dedispersion without a formula). */
+double tbo_dispersion_constant(void) { return 4.148808e3; }
+
+int64_t tbo_dedisperse(const uint8_t* data, int32_t nchan, int64_t nsamp, double fch1_mhz, double foff_mhz,
+                       double tsamp, const double* dm, int32_t ndm, float* out)
+{
+    if (!data || nchan < 1 || nsamp < 1 || !(tsamp > 0.0) || !dm || ndm < 1 || !(fch1_mhz > 0.0)) return -1;
+    double ftop = fch1_mhz > fch1_mhz + (nchan - 1) * foff_mhz ? fch1_mhz : fch1_mhz + (nchan - 1) * foff_mhz;
+    double fbot = fch1_mhz < fch1_mhz + (nchan - 1) * foff_mhz ? fch1_mhz : fch1_mhz + (nchan - 1) * foff_mhz;
+    if (!(fbot > 0.0)) return -1;
+    int64_t* s = (int64_t*)malloc(sizeof(int64_t) * (size_t)ndm * (size_t)nchan);
+    if (!s) return -1;
+    int64_t smax = 0;
+    for (int32_t d = 0; d < ndm; ++d) {
+        if (!(dm[d] >= 0.0)) {
+            free(s);
+            return -1;
+        }
+        for (int32_t c = 0; c < nchan; ++c) {
+            double f = fch1_mhz + c * foff_mhz;
+            double delay = tbo_dispersion_constant() * dm[d] * (1.0 / (f * f) - 1.0 / (ftop * ftop));
+            int64_t v = (int64_t)rint(delay / tsamp);
+            s[(size_t)d * nchan + c] = v;
+            if (v > smax) smax = v;
+        }
+    }
+    int64_t nout = nsamp - smax;
+    if (nout < 1) {
+        free(s);
+        return -1;
+    }
+    if (out)
+        for (int32_t d = 0; d < ndm; ++d)
+            for (int64_t t = 0; t < nout; ++t) {
+                double acc = 0.0;
+                for (int32_t c = 0; c < nchan; ++c) acc += (double)data[(size_t)(t + s[(size_t)d * nchan + c]) * nchan + c];
+                out[(size_t)d * nout + t] = (float)acc;
+            }
+    free(s);
+    return nout;
+}

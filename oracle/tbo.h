@@ -12,6 +12,9 @@
  * share no code, tables or constants.
  *
  * Steps and the passages they follow:
+ *   O0 dedispersion ......... incoherent shift-and-add over channels, the
+ *                             step before the search (App. A, Sec. 5.2;
+ *                             the paper names it without a formula)
  *   O1 mean removal ......... zero-mean convention of the mean-padding remark
  *                             (Sec. 2.8, Template Bank Verification)
  *   O2 mean anomaly ......... Kepler equation, Sec. 2.1 (M = Omega t + alpha)
@@ -153,6 +156,17 @@ int tbo_template_stages(const float* x0, const tbo_config* cfg, const tbo_templa
 int tbo_search(const float* x0, const tbo_config* cfg, const tbo_template* t,
                uint32_t count, uint32_t first_template_id, uint32_t series_id,
                int32_t nthreads, tbo_candidate* out, int64_t capacity, int64_t* n_total);
+
+/* O0 dedispersion (upstream of the search; App. A, Sec. 5.2): the series for
+ * dispersion measure dm[d] is out[d * nout + t] = sum over channels c of
+ * data[(t + s_dc) * nchan + c] for t < nout, data time-major 8-bit, channel c
+ * at f_c = fch1 + c foff [MHz], s_dc = rint(K_DM dm[d] (f_c^-2 - f_top^-2) / tsamp)
+ * with f_top the highest channel frequency and K_DM the dispersion constant
+ * (tbo_dispersion_constant); nout = nsamp - max over d, c of s_dc.
+ * Returns nout, or -1 on bad arguments (nout < 1 included). */
+double tbo_dispersion_constant(void);
+int64_t tbo_dedisperse(const uint8_t* data, int32_t nchan, int64_t nsamp, double fch1_mhz, double foff_mhz,
+                       double tsamp, const double* dm, int32_t ndm, float* out);
 
 /* O11 candidate grouping: the kept candidates (strongest of each group) in
  * strength order into out (n records), their group sizes into group (may be

@@ -9,6 +9,7 @@ import pytest
 import oracle
 from tests import test_oracle_end_to_end as E2E
 from tests import test_oracle_pins as PINS
+from tests import test_oracle_dedisperse as DD
 from tests import test_oracle_distill as DS
 from tests import test_oracle_ell as ELL
 from tests import test_oracle_series_whitening as SW
@@ -63,6 +64,11 @@ MUTANTS = {
     "zap_open_high_end": ("if ((double)k >= lo && (double)k <= hi) phat[k] = 0.0;",
                           "if ((double)k >= lo && (double)k < hi) phat[k] = 0.0;"),
     "zap_not_applied": ("    tbo_zap(w->phat, nb, (double)n * c->tsamp, c->zap_lo_hz, c->zap_hi_hz, c->nzap);\n", ""),
+    "dedisp_delay_from_bottom": ("(1.0 / (f * f) - 1.0 / (ftop * ftop))", "(1.0 / (ftop * ftop) - 1.0 / (f * f))"),
+    "dedisp_truncated_delay": ("int64_t v = (int64_t)rint(delay / tsamp);", "int64_t v = (int64_t)(delay / tsamp);"),
+    "dedisp_read_backwards": ("data[(size_t)(t + s[(size_t)d * nchan + c]) * nchan + c]",
+                              "data[(size_t)(t + smax - s[(size_t)d * nchan + c]) * nchan + c]"),
+    "dedisp_constant": ("return 4.148808e3;", "return 4.148808e3 * 1.0005;"),
     "fold_pick_index": ("for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * hp)];",
                         "for (int64_t mm = 1; mm < h; mm += 2) acc += w->phat[(2 * mm * k + 2 * hp) / (4 * h)];"),
 }
@@ -91,6 +97,9 @@ def _pins():
     for f in [ELL.test_zero_eccentricity_is_the_circular_bt_delay, ELL.test_series_indices_follow_the_exact_delay]:
         out.append(lambda f=f: f(None))
     for f in [ZP.test_zapped_bins_are_zero_and_the_rest_untouched, ZP.test_zap_function_edges]:
+        out.append(lambda f=f: f(None))
+    for f in [DD.test_dispersion_constant_from_codata, DD.test_zero_dm_is_the_channel_sum,
+              DD.test_impulse_lands_at_its_delay, DD.test_band_order_does_not_matter]:
         out.append(lambda f=f: f(None))
     for f in [DS.test_hand_worked_example, DS.test_tolerance_is_measured_at_the_ratio,
               DS.test_relative_tolerance_scales_with_the_target, DS.test_same_frequency_only]:
