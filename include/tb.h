@@ -225,6 +225,30 @@ tb_status tb_profile_read(tb_plan_t plan, double ms[6], uint64_t launches[6], ui
  * copy.  A measurement utility: the practical HBM ceiling. */
 tb_status tb_stream_copy(tb_plan_t plan, void* dst, const void* src, uint64_t bytes, uint32_t reps, double* ms);
 
+/* Incoherent dedispersion, the step that produces the searched series (App.
+ * A.1 and Sec. 5.2 run it before the orbital search; no formula is given).
+ * data: 8-bit filterbank, time-major (sample t's channels at t * nchan), host
+ * or device memory (flags TB_MEM_HOST / TB_MEM_DEVICE).  Channel c is at
+ * fch1 + c foff MHz (foff may be negative).  For each DM dm[d] (pc cm^-3, >= 0)
+ * the series out[d * nout + t] = sum_c x_c[t + s_dc], s_dc = rint(4.148808e3
+ * dm (f_c^-2 - f_top^-2) / tsamp) samples behind the highest frequency f_top,
+ * nout = nsamp - max s_dc (the samples every channel covers).  out is a
+ * device array of ndm * nout floats owned by the caller (pass NULL to get
+ * *nout only); the sums are exact.  The call allocates scratch of nchan *
+ * nsamp bytes (twice for host data) for its duration and waits for the
+ * result; *kernel_ms (may be NULL) receives the device time.
+ * TB_ERR_INVALID_ARG for bad sizes (nchan 1..8192, nsamp < 2^31, ndm 1..2^20),
+ * negative or non-finite DMs, a band reaching 0 Hz, or delays beyond the data. */
+typedef struct {
+    uint32_t nchan;
+    uint64_t nsamp;
+    double fch1_mhz;
+    double foff_mhz;
+    double tsamp_s;
+} tb_filterbank;
+tb_status tb_dedisperse(tb_plan_t plan, const tb_filterbank* fb, const uint8_t* data, uint32_t flags, const double* dm,
+                        uint32_t ndm, float* out, uint64_t* nout, double* kernel_ms);
+
 /* Random template bank (Secs. 2.3-2.7).  Proper-volume density of the bank
  * at the given points: the square root of the determinant of the phase
  * metric (Sec. 2.2: time averages of products of phase derivatives, minus the

@@ -85,12 +85,17 @@ EXPORTS = [
     "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
-    "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density",
+    "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density", "tb_dedisperse",
 ]
 
 
 class TbBankMetric(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("nodes", C.c_uint32), ("tobs_s", C.c_double), ("fmax_hz", C.c_double)]
+
+
+class TbFilterbank(C.Structure):
+    _fields_ = [("nchan", C.c_uint32), ("nsamp", C.c_uint64), ("fch1_mhz", C.c_double), ("foff_mhz", C.c_double),
+                ("tsamp_s", C.c_double)]
 
 
 class TbError(RuntimeError):
@@ -139,6 +144,7 @@ def _load():
     L.tb_distill.argtypes = [vp, u64, u32, u32, u32, vp, vp, P(u64)]
     L.tb_zap_series.argtypes = [vp, i32, vp, vp, u32]
     L.tb_bank_density.argtypes = [vp, P(TbBankMetric), vp, u64, vp, P(C.c_double)]
+    L.tb_dedisperse.argtypes = [vp, P(TbFilterbank), vp, u32, vp, u32, vp, P(u64), P(C.c_double)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tb_default_config", "tb_strerror"):
@@ -291,6 +297,27 @@ def tb_bank_density(plan: int, kind: int, tobs_s: float, fmax_hz: float, points,
     return out[: pts.size], ms.value
 
 
+def tb_dedisperse(plan: int, data, fch1_mhz: float, foff_mhz: float, tsamp_s: float, dms, out=None,
+                  nchan: int | None = None, nsamp: int | None = None):
+    """data: uint8 (nsamp, nchan) numpy array (host) or a device address with
+    nchan and nsamp given.  out: device address of ndm * nout floats, or None
+    to only compute nout.  Returns (nout, kernel milliseconds)."""
+    flags = TB_MEM_HOST
+    if isinstance(data, int):
+        flags = TB_MEM_DEVICE
+    else:
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        nsamp, nchan = data.shape
+    dm = np.ascontiguousarray(dms, dtype=np.float64)
+    fb = TbFilterbank(int(nchan), int(nsamp), float(fch1_mhz), float(foff_mhz), float(tsamp_s))
+    nout = C.c_uint64(0)
+    ms = C.c_double(0.0)
+    _check(_L.tb_dedisperse(C.c_void_p(plan), C.byref(fb), _ptr(data), flags, _ptr(dm), dm.size,
+                            C.c_void_p(out) if out is not None else None, C.byref(nout), C.byref(ms)),
+           "tb_dedisperse")
+    return nout.value, ms.value
+
+
 def tb_zap_series(plan: int, series_id: int, intervals) -> None:
     """intervals: (lo_hz, hi_hz) pairs whose bins are zeroed after whitening
     for every later search on the series; empty clears the list."""
@@ -387,6 +414,9 @@ class Plan:
 
     def bank_density(self, kind, tobs_s, fmax_hz, points, nodes=128):
         return tb_bank_density(self.handle, kind, tobs_s, fmax_hz, points, nodes)
+
+    def dedisperse(self, data, fch1_mhz, foff_mhz, tsamp_s, dms, out=None, nchan=None, nsamp=None):
+        return tb_dedisperse(self.handle, data, fch1_mhz, foff_mhz, tsamp_s, dms, out, nchan, nsamp)
 
     def zap(self, sid, intervals):
         """Birdie intervals (lo_hz, hi_hz) for the series; [] clears them."""

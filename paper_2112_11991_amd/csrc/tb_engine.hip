@@ -770,6 +770,78 @@ tb_status tb_unload_series(tb_plan_t p, int32_t id)
     return TB_OK;
 }
 
+tb_status tb_dedisperse(tb_plan_t p, const tb_filterbank* fb, const uint8_t* data, uint32_t flags, const double* dm,
+                        uint32_t ndm, float* out, uint64_t* nout, double* kernel_ms)
+{
+    if (!p || !fb || !data || !dm || !nout || ndm < 1 || ndm > (1u << 20) || fb->nchan < 1 || fb->nchan > 8192 ||
+        fb->nsamp < 1 || fb->nsamp >= (1ull << 31) || !(fb->tsamp_s > 0.0) || !std::isfinite(fb->tsamp_s) ||
+        !std::isfinite(fb->fch1_mhz) || !std::isfinite(fb->foff_mhz) || (flags != TB_MEM_HOST && flags != TB_MEM_DEVICE))
+        return TB_ERR_INVALID_ARG;
+    const double flast = fb->fch1_mhz + (double)(fb->nchan - 1) * fb->foff_mhz;
+    if (!(std::min(fb->fch1_mhz, flast) > 0.0)) return TB_ERR_INVALID_ARG;
+    for (uint32_t d = 0; d < ndm; ++d)
+        if (!(dm[d] >= 0.0) || !std::isfinite(dm[d])) return TB_ERR_INVALID_ARG;
+    const int nchan = (int)fb->nchan;
+    const int64_t nsamp = (int64_t)fb->nsamp;
+    std::vector<int32_t> delay;
+    int ldd = 0;
+    const int64_t smax = dedisp_delays(nchan, fb->fch1_mhz, fb->foff_mhz, fb->tsamp_s, dm, (int)ndm, delay, ldd);
+    if (smax >= nsamp) return TB_ERR_INVALID_ARG;
+    *nout = (uint64_t)(nsamp - smax);
+    if (kernel_ms) *kernel_ms = 0.0;
+    if (!out) return TB_OK;
+    const int tile = dedisp_tile(), ntile = ldd / tile;
+    std::vector<int2> lospan((size_t)nchan * ntile);
+    for (int c = 0; c < nchan; ++c)
+        for (int g = 0; g < ntile; ++g) {
+            int lo = delay[(size_t)c * ldd + g * tile], hi = lo;
+            for (int j = 1; j < tile; ++j) {
+                const int v = delay[(size_t)c * ldd + g * tile + j];
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            lospan[(size_t)c * ntile + g] = make_int2(lo, hi - lo);
+        }
+    std::lock_guard<std::mutex> lk(p->mu);
+    TB_TRY(hipSetDevice(p->cfg.device));
+    // scratch: [time-major copy of host data] channel-major bytes, delays, tile bounds
+    const size_t bytes = (size_t)nchan * (size_t)nsamp;
+    const size_t bdel = sizeof(int32_t) * delay.size(), blo = sizeof(int2) * lospan.size();
+    uint8_t *d_tm = nullptr, *d_cm = nullptr;
+    int32_t* d_delay = nullptr;
+    int2* d_lospan = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    tb_status st = TB_OK;
+    if ((flags == TB_MEM_HOST && hipMalloc(&d_tm, bytes) != hipSuccess) || hipMalloc(&d_cm, bytes) != hipSuccess ||
+        hipMalloc(&d_delay, bdel) != hipSuccess || hipMalloc(&d_lospan, blo) != hipSuccess)
+        st = TB_ERR_OOM;
+    const uint8_t* src = flags == TB_MEM_HOST ? d_tm : data;
+    if (!st && ((flags == TB_MEM_HOST && hipMemcpyAsync(d_tm, data, bytes, hipMemcpyHostToDevice, p->stream) != hipSuccess) ||
+                hipMemcpyAsync(d_delay, delay.data(), bdel, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+                hipMemcpyAsync(d_lospan, lospan.data(), blo, hipMemcpyHostToDevice, p->stream) != hipSuccess))
+        st = TB_ERR_DEVICE;
+    if (!st && kernel_ms && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess ||
+                             hipEventRecord(ev[0], p->stream) != hipSuccess))
+        st = TB_ERR_DEVICE;
+    if (!st && launch_dedisperse(src, d_cm, nchan, nsamp, d_delay, ldd, d_lospan, (int)ndm, (int64_t)*nout, out,
+                                 p->stream) != hipSuccess)
+        st = TB_ERR_DEVICE;
+    if (!st && kernel_ms && hipEventRecord(ev[1], p->stream) != hipSuccess) st = TB_ERR_DEVICE;
+    if (hipStreamSynchronize(p->stream) != hipSuccess && !st) st = TB_ERR_DEVICE;
+    if (!st && kernel_ms) {
+        float f = 0.0f;
+        if (hipEventElapsedTime(&f, ev[0], ev[1]) != hipSuccess) st = TB_ERR_DEVICE;
+        *kernel_ms = f;
+    }
+    for (hipEvent_t e : ev)
+        if (e) hipEventDestroy(e);
+    hipFree(d_tm);
+    hipFree(d_cm);
+    hipFree(d_delay);
+    hipFree(d_lospan);
+    return st;
+}
+
 tb_status tb_bank_density(tb_plan_t p, const tb_bank_metric* m, const tb_template* pts, uint64_t count,
                           double* out, double* kernel_ms)
 {

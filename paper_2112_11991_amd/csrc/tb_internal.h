@@ -151,6 +151,15 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s)
 // Rewrites a mean-removed series into the tile order pass 1 reads.
 hipError_t launch_tile_series(const Geometry& g, const float* in, float* out, hipStream_t s);
 int harmsum_tile();
+// Dedispersion: integer delays delay[c * ldd + d] (ldd = ndm rounded up to the
+// DM tile) of every channel and trial; returns the largest.
+int64_t dedisp_delays(int nchan, double fch1, double foff, double tsamp, const double* dm, int ndm,
+                      std::vector<int32_t>& delay, int& ldd);
+// Transposes d_tm (time-major, may be null if d_cm already holds channel-major
+// bytes) into d_cm, then dedisperses into out (ndm x nout floats).
+hipError_t launch_dedisperse(const uint8_t* d_tm, uint8_t* d_cm, int nchan, int64_t nsamp, const int32_t* d_delay,
+                             int ldd, const int2* d_lospan, int ndm, int64_t nout, float* out, hipStream_t s);
+int dedisp_tile();
 // Bank density of count points (device arrays); kind 0 circular, 1 elliptical;
 // waits for the stream; *ms (may be null) receives the kernel time.
 hipError_t launch_bank_density(int kind, int nodes, double T, double fmax, const tb_template* d_pts, uint32_t count,
