@@ -172,6 +172,42 @@ def grouping_report(tb, cands, with_oracle: bool):
     return rep
 
 
+def dedispersion_report(tb, torch, with_oracle: bool):
+    """Dedispersion of an 8-bit filterbank shaped like the paper's simulations
+    (Table 2: 1024 channels from 1181.8 MHz by 0.390625 MHz, 256 us) over
+    2^20 samples (1 GiB, device-resident) into 128 DM trials 0-500 pc cm^-3.
+    Rate in channel-sample additions per second of device time (one LDS byte
+    read and one integer add each), against the chip's VALU issue rate of
+    256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz; the oracle timed on a sample."""
+    nchan, nsamp, ndm = 1024, 1 << 20, 128
+    f1, df, ts = 1181.804688, 0.390625, 256e-6
+    dms = np.linspace(0.0, 500.0, ndm)
+    g = torch.Generator(device="cuda").manual_seed(2112)
+    x = torch.randint(0, 256, (nsamp, nchan), dtype=torch.uint8, device="cuda", generator=g)
+    with tb.Plan() as plan:
+        nout, _ = plan.dedisperse(x.data_ptr(), f1, df, ts, dms, nchan=nchan, nsamp=nsamp)
+        out = torch.empty(ndm * nout, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        plan.dedisperse(x.data_ptr(), f1, df, ts, dms, out=out.data_ptr(), nchan=nchan, nsamp=nsamp)
+        _, ms = plan.dedisperse(x.data_ptr(), f1, df, ts, dms, out=out.data_ptr(), nchan=nchan, nsamp=nsamp)
+    adds = float(nchan) * nout * ndm
+    peak = 256 * 4 * 16 * 2.4e9
+    rep = {"workload": "1024 channels x 2^20 samples (8 bit, 256 us) -> 128 DM trials 0-500", "kernel_ms": ms,
+           "value": adds / (ms * 1e-3), "unit": "channel-sample adds/s", "peak": peak, "frac": adds / (ms * 1e-3) / peak,
+           "input_gbs": nchan * nsamp / (ms * 1e-3) / 1e9}
+    del x, out
+    if with_oracle:
+        import oracle
+
+        oracle.build()
+        xs = np.random.default_rng(1).integers(0, 256, (20000, 64)).astype(np.uint8)
+        t0 = time.perf_counter()
+        o = oracle.dedisperse(xs, f1, df * 16, ts, dms[:8])
+        dt = time.perf_counter() - t0
+        rep["oracle"] = {"value": o.size * 64 / dt, "sample": "64 channels x 20000 samples x 8 DMs", "cores": 1}
+    return rep
+
+
 def bank_report(tb, with_oracle: bool):
     """Random-template-bank density kernel on the Table 1 prior region
     (T = 1.2 h, f_max = 66.67 Hz, P_orb 6-12 h, 1.4 + 8 solar masses; e < 0.1
@@ -317,6 +353,7 @@ def run_bank(args, tb, torch):
                                       not args.no_cpu_baseline)
     if args.workload == "c2":
         out["bank"] = bank_report(tb, not args.no_cpu_baseline)
+        out["dedispersion"] = dedispersion_report(tb, torch, not args.no_cpu_baseline)
     if args.workload == "c4" and not args.no_plain:
         idx = list(range(min(4, len(w.series))))
         rates = plain_vs_batched(tb, w, idx, 256)
