@@ -806,13 +806,15 @@ tb_status tb_dedisperse(tb_plan_t p, const tb_filterbank* fb, const uint8_t* dat
     TB_TRY(hipSetDevice(p->cfg.device));
     // scratch: [time-major copy of host data] channel-major bytes, delays, tile bounds
     const size_t bytes = (size_t)nchan * (size_t)nsamp;
+    const int64_t ldx = (nsamp + 15) & ~(int64_t)15;  // channel-major rows, 16-byte aligned
+    const size_t bcm = (size_t)nchan * (size_t)ldx;
     const size_t bdel = sizeof(int32_t) * delay.size(), blo = sizeof(int2) * lospan.size();
     uint8_t *d_tm = nullptr, *d_cm = nullptr;
     int32_t* d_delay = nullptr;
     int2* d_lospan = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
     tb_status st = TB_OK;
-    if ((flags == TB_MEM_HOST && hipMalloc(&d_tm, bytes) != hipSuccess) || hipMalloc(&d_cm, bytes) != hipSuccess ||
+    if ((flags == TB_MEM_HOST && hipMalloc(&d_tm, bytes) != hipSuccess) || hipMalloc(&d_cm, bcm) != hipSuccess ||
         hipMalloc(&d_delay, bdel) != hipSuccess || hipMalloc(&d_lospan, blo) != hipSuccess)
         st = TB_ERR_OOM;
     const uint8_t* src = flags == TB_MEM_HOST ? d_tm : data;
@@ -823,7 +825,7 @@ tb_status tb_dedisperse(tb_plan_t p, const tb_filterbank* fb, const uint8_t* dat
     if (!st && kernel_ms && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess ||
                              hipEventRecord(ev[0], p->stream) != hipSuccess))
         st = TB_ERR_DEVICE;
-    if (!st && launch_dedisperse(src, d_cm, nchan, nsamp, d_delay, ldd, d_lospan, (int)ndm, (int64_t)*nout, out,
+    if (!st && launch_dedisperse(src, d_cm, nchan, nsamp, ldx, d_delay, ldd, d_lospan, (int)ndm, (int64_t)*nout, out,
                                  p->stream) != hipSuccess)
         st = TB_ERR_DEVICE;
     if (!st && kernel_ms && hipEventRecord(ev[1], p->stream) != hipSuccess) st = TB_ERR_DEVICE;
