@@ -227,20 +227,23 @@ tb_status tb_stream_copy(tb_plan_t plan, void* dst, const void* src, uint64_t by
 
 /* Incoherent dedispersion, the step that produces the searched series (App.
  * A.1 and Sec. 5.2 run it before the orbital search; no formula is given).
- * data: 8-bit filterbank, time-major (sample t's channels at t * nchan), host
- * or device memory (flags TB_MEM_HOST / TB_MEM_DEVICE).  Channel c is at
+ * data: 8- or 4-bit filterbank, time-major (sample t's channels together),
+ * host or device memory (flags TB_MEM_HOST / TB_MEM_DEVICE).  Channel c is at
  * fch1 + c foff MHz (foff may be negative).  For each DM dm[d] (pc cm^-3, >= 0)
  * the series out[d * nout + t] = sum_c x_c[t + s_dc], s_dc = rint(4.148808e3
  * dm (f_c^-2 - f_top^-2) / tsamp) samples behind the highest frequency f_top,
  * nout = nsamp - max s_dc (the samples every channel covers).  out is a
  * device array of ndm * nout floats owned by the caller (pass NULL to get
- * *nout only); the sums are exact.  The call allocates scratch of nchan *
- * nsamp bytes (twice for host data) for its duration and waits for the
- * result; *kernel_ms (may be NULL) receives the device time.
+ * *nout only); the sums are exact.  The call allocates scratch of about
+ * nchan * nsamp bytes (plus the packed input for host data) for its duration
+ * and waits for the result; *kernel_ms (may be NULL) receives the device
+ * time.
  * TB_ERR_INVALID_ARG for bad sizes (nchan 1..8192, nsamp < 2^31, ndm 1..2^20),
  * negative or non-finite DMs, a band reaching 0 Hz, or delays beyond the data. */
 typedef struct {
     uint32_t nchan;
+    uint32_t nbits;    /* 8, or 4: two channels per byte, the even channel in the low nibble
+                          (nchan even); 0 means 8 */
     uint64_t nsamp;
     double fch1_mhz;
     double foff_mhz;

@@ -172,8 +172,8 @@ def _bind(L):
     L.tbo_search.restype = C.c_int
     L.tbo_dispersion_constant.argtypes = []
     L.tbo_dispersion_constant.restype = C.c_double
-    L.tbo_dedisperse.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_double, C.c_double, C.c_void_p,
-                                 C.c_int32, C.c_void_p]
+    L.tbo_dedisperse.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int64, C.c_double, C.c_double, C.c_double,
+                                 C.c_void_p, C.c_int32, C.c_void_p]
     L.tbo_dedisperse.restype = C.c_int64
     L.tbo_distill.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
                               P(C.c_int64)]
@@ -393,16 +393,21 @@ def dispersion_constant() -> float:
     return lib().tbo_dispersion_constant()
 
 
-def dedisperse(data: np.ndarray, fch1_mhz: float, foff_mhz: float, tsamp: float, dms) -> np.ndarray:
-    """data: uint8 (nsamp, nchan), time-major.  Returns (ndm, nout) float32."""
+def dedisperse(data: np.ndarray, fch1_mhz: float, foff_mhz: float, tsamp: float, dms, nbits: int = 8,
+               nchan: int | None = None) -> np.ndarray:
+    """data: uint8 (nsamp, nchan) time-major 8-bit samples, or for nbits = 4
+    (nsamp, nchan / 2) bytes of packed pairs (nchan given).  Returns (ndm, nout)
+    float32."""
     data = np.ascontiguousarray(data, dtype=np.uint8)
-    nsamp, nchan = data.shape
+    nsamp = data.shape[0]
+    if nbits == 8:
+        nchan = data.shape[1]
     dm = np.ascontiguousarray(dms, dtype=np.float64)
-    nout = lib().tbo_dedisperse(_ptr(data), nchan, nsamp, float(fch1_mhz), float(foff_mhz), float(tsamp), _ptr(dm),
-                                dm.size, None)
+    args = (_ptr(data), int(nbits), int(nchan), nsamp, float(fch1_mhz), float(foff_mhz), float(tsamp), _ptr(dm),
+            dm.size)
+    nout = lib().tbo_dedisperse(*args, None)
     if nout < 1:
         raise ValueError("tbo_dedisperse: bad arguments")
     out = np.empty((dm.size, nout), dtype=np.float32)
-    lib().tbo_dedisperse(_ptr(data), nchan, nsamp, float(fch1_mhz), float(foff_mhz), float(tsamp), _ptr(dm), dm.size,
-                         _ptr(out))
+    lib().tbo_dedisperse(*args, _ptr(out))
     return out

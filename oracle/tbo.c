@@ -745,10 +745,21 @@ int tbo_distill(const tbo_candidate* in, int64_t n, int32_t max_ratio, int64_t t
  * s MHz^2 pc^-1 cm^3 (the paper names dedispersion without a formula). */
 double tbo_dispersion_constant(void) { return 4.148808e3; }
 
-int64_t tbo_dedisperse(const uint8_t* data, int32_t nchan, int64_t nsamp, double fch1_mhz, double foff_mhz,
-                       double tsamp, const double* dm, int32_t ndm, float* out)
+/* Sample (t, c) of a time-major filterbank of 8-bit values, or of 4-bit
+ * values packed two channels per byte with the even channel in the low
+ * nibble. */
+static unsigned fb_sample(const uint8_t* data, int32_t nbits, int32_t nchan, int64_t t, int32_t c)
+{
+    if (nbits == 8) return data[(size_t)t * nchan + c];
+    uint8_t b = data[((size_t)t * nchan + c) / 2];
+    return (c % 2 == 0) ? (b & 15u) : (b >> 4);
+}
+
+int64_t tbo_dedisperse(const uint8_t* data, int32_t nbits, int32_t nchan, int64_t nsamp, double fch1_mhz,
+                       double foff_mhz, double tsamp, const double* dm, int32_t ndm, float* out)
 {
     if (!data || nchan < 1 || nsamp < 1 || !(tsamp > 0.0) || !dm || ndm < 1 || !(fch1_mhz > 0.0)) return -1;
+    if (nbits != 8 && !(nbits == 4 && nchan % 2 == 0)) return -1;
     double ftop = fch1_mhz > fch1_mhz + (nchan - 1) * foff_mhz ? fch1_mhz : fch1_mhz + (nchan - 1) * foff_mhz;
     double fbot = fch1_mhz < fch1_mhz + (nchan - 1) * foff_mhz ? fch1_mhz : fch1_mhz + (nchan - 1) * foff_mhz;
     if (!(fbot > 0.0)) return -1;
@@ -777,7 +788,7 @@ int64_t tbo_dedisperse(const uint8_t* data, int32_t nchan, int64_t nsamp, double
         for (int32_t d = 0; d < ndm; ++d)
             for (int64_t t = 0; t < nout; ++t) {
                 double acc = 0.0;
-                for (int32_t c = 0; c < nchan; ++c) acc += (double)data[(size_t)(t + s[(size_t)d * nchan + c]) * nchan + c];
+                for (int32_t c = 0; c < nchan; ++c) acc += (double)fb_sample(data, nbits, nchan, t + s[(size_t)d * nchan + c], c);
                 out[(size_t)d * nout + t] = (float)acc;
             }
     free(s);

@@ -159,14 +159,15 @@ int tbo_search(const float* x0, const tbo_config* cfg, const tbo_template* t,
 
 /* O0 dedispersion (upstream of the search; App. A, Sec. 5.2): the series for
  * dispersion measure dm[d] is out[d * nout + t] = sum over channels c of
- * data[(t + s_dc) * nchan + c] for t < nout, data time-major 8-bit, channel c
+ * x[t + s_dc][c] for t < nout, x time-major 8-bit samples (or 4-bit: two
+ * channels per byte, the even channel in the low nibble), channel c
  * at f_c = fch1 + c foff [MHz], s_dc = rint(K_DM dm[d] (f_c^-2 - f_top^-2) / tsamp)
  * with f_top the highest channel frequency and K_DM the dispersion constant
  * (tbo_dispersion_constant); nout = nsamp - max over d, c of s_dc.
  * Returns nout, or -1 on bad arguments (nout < 1 included). */
 double tbo_dispersion_constant(void);
-int64_t tbo_dedisperse(const uint8_t* data, int32_t nchan, int64_t nsamp, double fch1_mhz, double foff_mhz,
-                       double tsamp, const double* dm, int32_t ndm, float* out);
+int64_t tbo_dedisperse(const uint8_t* data, int32_t nbits, int32_t nchan, int64_t nsamp, double fch1_mhz,
+                       double foff_mhz, double tsamp, const double* dm, int32_t ndm, float* out);
 
 /* O11 candidate grouping: the kept candidates (strongest of each group) in
  * strength order into out (n records), their group sizes into group (may be

@@ -94,8 +94,8 @@ class TbBankMetric(C.Structure):
 
 
 class TbFilterbank(C.Structure):
-    _fields_ = [("nchan", C.c_uint32), ("nsamp", C.c_uint64), ("fch1_mhz", C.c_double), ("foff_mhz", C.c_double),
-                ("tsamp_s", C.c_double)]
+    _fields_ = [("nchan", C.c_uint32), ("nbits", C.c_uint32), ("nsamp", C.c_uint64), ("fch1_mhz", C.c_double),
+                ("foff_mhz", C.c_double), ("tsamp_s", C.c_double)]
 
 
 class TbError(RuntimeError):
@@ -298,18 +298,21 @@ def tb_bank_density(plan: int, kind: int, tobs_s: float, fmax_hz: float, points,
 
 
 def tb_dedisperse(plan: int, data, fch1_mhz: float, foff_mhz: float, tsamp_s: float, dms, out=None,
-                  nchan: int | None = None, nsamp: int | None = None):
-    """data: uint8 (nsamp, nchan) numpy array (host) or a device address with
-    nchan and nsamp given.  out: device address of ndm * nout floats, or None
-    to only compute nout.  Returns (nout, kernel milliseconds)."""
+                  nchan: int | None = None, nsamp: int | None = None, nbits: int = 8):
+    """data: uint8 (nsamp, nchan) numpy array of 8-bit samples (or, nbits = 4,
+    (nsamp, nchan / 2) packed pairs with nchan given) on the host, or a device
+    address with nchan and nsamp given.  out: device address of ndm * nout
+    floats, or None to only compute nout.  Returns (nout, kernel milliseconds)."""
     flags = TB_MEM_HOST
     if isinstance(data, int):
         flags = TB_MEM_DEVICE
     else:
         data = np.ascontiguousarray(data, dtype=np.uint8)
-        nsamp, nchan = data.shape
+        nsamp = data.shape[0]
+        if nbits == 8:
+            nchan = data.shape[1]
     dm = np.ascontiguousarray(dms, dtype=np.float64)
-    fb = TbFilterbank(int(nchan), int(nsamp), float(fch1_mhz), float(foff_mhz), float(tsamp_s))
+    fb = TbFilterbank(int(nchan), int(nbits), int(nsamp), float(fch1_mhz), float(foff_mhz), float(tsamp_s))
     nout = C.c_uint64(0)
     ms = C.c_double(0.0)
     _check(_L.tb_dedisperse(C.c_void_p(plan), C.byref(fb), _ptr(data), flags, _ptr(dm), dm.size,
@@ -415,8 +418,8 @@ class Plan:
     def bank_density(self, kind, tobs_s, fmax_hz, points, nodes=128):
         return tb_bank_density(self.handle, kind, tobs_s, fmax_hz, points, nodes)
 
-    def dedisperse(self, data, fch1_mhz, foff_mhz, tsamp_s, dms, out=None, nchan=None, nsamp=None):
-        return tb_dedisperse(self.handle, data, fch1_mhz, foff_mhz, tsamp_s, dms, out, nchan, nsamp)
+    def dedisperse(self, data, fch1_mhz, foff_mhz, tsamp_s, dms, out=None, nchan=None, nsamp=None, nbits=8):
+        return tb_dedisperse(self.handle, data, fch1_mhz, foff_mhz, tsamp_s, dms, out, nchan, nsamp, nbits)
 
     def zap(self, sid, intervals):
         """Birdie intervals (lo_hz, hi_hz) for the series; [] clears them."""

@@ -29,8 +29,10 @@ constexpr int DD_CH = 4;                 // channels staged per step
 constexpr int DD_SEGD = 1024;            // staged dwords per channel (4096 bytes)
 constexpr int DD_SPAN = 4 * DD_SEGD - DD_TT - 8;  // delay spread a staged channel may have (3064)
 
-// 64 x 64 byte tiles: in[t][c] (time-major) -> out[c][t] with rows of ldx
+// 64 x 64 sample tiles: in (time-major, 8-bit samples or 4-bit pairs with
+// the even channel in the low nibble) -> out[c][t] bytes with rows of ldx
 // bytes; the row padding beyond nsamp is zeroed.
+template <int NBITS>
 __global__ __launch_bounds__(256) void k_fb_transpose(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
                                                       int nchan, int64_t nsamp, int64_t ldx)
 {
@@ -41,7 +43,16 @@ __global__ __launch_bounds__(256) void k_fb_transpose(const uint8_t* __restrict_
     for (int r = ty; r < 64; r += 4) {
         const int64_t t = t0 + r;
         const int c = c0 + tx;
-        tile[r][tx] = (t < nsamp && c < nchan) ? in[t * nchan + c] : (uint8_t)0;
+        uint8_t v = 0;
+        if (t < nsamp && c < nchan) {
+            if constexpr (NBITS == 8) {
+                v = in[t * nchan + c];
+            } else {
+                const uint8_t b = in[(t * nchan + c) >> 1];
+                v = (c & 1) ? (uint8_t)(b >> 4) : (uint8_t)(b & 15u);
+            }
+        }
+        tile[r][tx] = v;
     }
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
@@ -170,13 +181,16 @@ int64_t dedisp_delays(int nchan, double fch1, double foff, double tsamp, const d
     return smax;
 }
 
-hipError_t launch_dedisperse(const uint8_t* d_tm, uint8_t* d_cm, int nchan, int64_t nsamp, int64_t ldx,
+hipError_t launch_dedisperse(const uint8_t* d_tm, int nbits, uint8_t* d_cm, int nchan, int64_t nsamp, int64_t ldx,
                              const int32_t* d_delay, int ldd, const int2* d_lospan, int ndm, int64_t nout, float* out,
                              hipStream_t s)
 {
     if (d_tm) {
         const dim3 tg((unsigned)((ldx + 63) / 64), (unsigned)((nchan + 63) / 64));
-        hipLaunchKernelGGL(k_fb_transpose, tg, dim3(256), 0, s, d_tm, d_cm, nchan, nsamp, ldx);
+        if (nbits == 4)
+            hipLaunchKernelGGL(k_fb_transpose<4>, tg, dim3(256), 0, s, d_tm, d_cm, nchan, nsamp, ldx);
+        else
+            hipLaunchKernelGGL(k_fb_transpose<8>, tg, dim3(256), 0, s, d_tm, d_cm, nchan, nsamp, ldx);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

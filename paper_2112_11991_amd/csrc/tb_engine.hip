@@ -777,6 +777,8 @@ tb_status tb_dedisperse(tb_plan_t p, const tb_filterbank* fb, const uint8_t* dat
         fb->nsamp < 1 || fb->nsamp >= (1ull << 31) || !(fb->tsamp_s > 0.0) || !std::isfinite(fb->tsamp_s) ||
         !std::isfinite(fb->fch1_mhz) || !std::isfinite(fb->foff_mhz) || (flags != TB_MEM_HOST && flags != TB_MEM_DEVICE))
         return TB_ERR_INVALID_ARG;
+    const int nbits = fb->nbits == 0 ? 8 : (int)fb->nbits;
+    if (nbits != 8 && !(nbits == 4 && fb->nchan % 2 == 0)) return TB_ERR_INVALID_ARG;
     const double flast = fb->fch1_mhz + (double)(fb->nchan - 1) * fb->foff_mhz;
     if (!(std::min(fb->fch1_mhz, flast) > 0.0)) return TB_ERR_INVALID_ARG;
     for (uint32_t d = 0; d < ndm; ++d)
@@ -805,7 +807,7 @@ tb_status tb_dedisperse(tb_plan_t p, const tb_filterbank* fb, const uint8_t* dat
     std::lock_guard<std::mutex> lk(p->mu);
     TB_TRY(hipSetDevice(p->cfg.device));
     // scratch: [time-major copy of host data] channel-major bytes, delays, tile bounds
-    const size_t bytes = (size_t)nchan * (size_t)nsamp;
+    const size_t bytes = (size_t)nchan * (size_t)nsamp / (nbits == 4 ? 2 : 1);  // packed input
     const int64_t ldx = (nsamp + 15) & ~(int64_t)15;  // channel-major rows, 16-byte aligned
     const size_t bcm = (size_t)nchan * (size_t)ldx;
     const size_t bdel = sizeof(int32_t) * delay.size(), blo = sizeof(int2) * lospan.size();
@@ -825,8 +827,8 @@ tb_status tb_dedisperse(tb_plan_t p, const tb_filterbank* fb, const uint8_t* dat
     if (!st && kernel_ms && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess ||
                              hipEventRecord(ev[0], p->stream) != hipSuccess))
         st = TB_ERR_DEVICE;
-    if (!st && launch_dedisperse(src, d_cm, nchan, nsamp, ldx, d_delay, ldd, d_lospan, (int)ndm, (int64_t)*nout, out,
-                                 p->stream) != hipSuccess)
+    if (!st && launch_dedisperse(src, nbits, d_cm, nchan, nsamp, ldx, d_delay, ldd, d_lospan, (int)ndm,
+                                 (int64_t)*nout, out, p->stream) != hipSuccess)
         st = TB_ERR_DEVICE;
     if (!st && kernel_ms && hipEventRecord(ev[1], p->stream) != hipSuccess) st = TB_ERR_DEVICE;
     if (hipStreamSynchronize(p->stream) != hipSuccess && !st) st = TB_ERR_DEVICE;

@@ -155,10 +155,10 @@ int harmsum_tile();
 // DM tile) of every channel and trial; returns the largest.
 int64_t dedisp_delays(int nchan, double fch1, double foff, double tsamp, const double* dm, int ndm,
                       std::vector<int32_t>& delay, int& ldd);
-// Transposes d_tm (time-major) into d_cm (channel-major rows of ldx bytes, a
-// multiple of 16, zero beyond nsamp), then dedisperses into out (ndm x nout
-// floats).
-hipError_t launch_dedisperse(const uint8_t* d_tm, uint8_t* d_cm, int nchan, int64_t nsamp, int64_t ldx,
+// Transposes d_tm (time-major, nbits 8 or 4) into d_cm (channel-major bytes,
+// rows of ldx bytes, a multiple of 16, zero beyond nsamp), then dedisperses
+// into out (ndm x nout floats).
+hipError_t launch_dedisperse(const uint8_t* d_tm, int nbits, uint8_t* d_cm, int nchan, int64_t nsamp, int64_t ldx,
                              const int32_t* d_delay, int ldd, const int2* d_lospan, int ndm, int64_t nout, float* out,
                              hipStream_t s);
 int dedisp_tile();

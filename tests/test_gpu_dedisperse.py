@@ -59,6 +59,33 @@ def test_dedispersion_matches_oracle_exactly(tb, nchan, nsamp, f1, df, ts, dms):
     assert np.array_equal(got2, want)
 
 
+def test_four_bit_filterbank_matches_oracle(tb):
+    """4-bit samples (two channels per byte, even channel in the low nibble),
+    Table 2's layout: host and device input, bit for bit against the oracle."""
+    import torch
+
+    nchan, nsamp, f1, df, ts = 256, 40000, 1181.804688, 0.390625, 256e-6
+    dms = np.linspace(0.0, 150.0, 21)
+    v = np.random.default_rng(8).integers(0, 16, (nsamp, nchan)).astype(np.uint8)
+    packed = np.ascontiguousarray(v[:, 0::2] | (v[:, 1::2] << 4))
+    want = oracle.dedisperse(packed, f1, df, ts, dms, nbits=4, nchan=nchan)
+    assert np.array_equal(want, oracle.dedisperse(v, f1, df, ts, dms))
+    with tb.Plan() as plan:
+        nout, _ = plan.dedisperse(packed, f1, df, ts, dms, nchan=nchan, nbits=4)
+        out = torch.empty(len(dms) * nout, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        plan.dedisperse(packed, f1, df, ts, dms, out=out.data_ptr(), nchan=nchan, nbits=4)
+        got = out.cpu().numpy().reshape(len(dms), nout)
+        pd = torch.from_numpy(packed).to("cuda:0")
+        out2 = torch.empty_like(out)
+        torch.cuda.synchronize()
+        plan.dedisperse(pd.data_ptr(), f1, df, ts, dms, out=out2.data_ptr(), nchan=nchan, nsamp=nsamp, nbits=4)
+        got2 = out2.cpu().numpy().reshape(len(dms), nout)
+        with pytest.raises(tb.TbError):
+            plan.dedisperse(packed[:, :3], f1, df, ts, dms, nchan=5, nbits=4)
+    assert np.array_equal(got, want) and np.array_equal(got2, want)
+
+
 def test_dedispersed_binary_pulsar_is_found(tb):
     """A 16-channel filterbank holding a binary pulsar dispersed at DM 60:
     dedispersed on the GPU, the DM-60 series is loaded straight from device

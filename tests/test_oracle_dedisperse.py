@@ -84,6 +84,19 @@ def test_band_order_does_not_matter(oracle_lib):
     assert np.array_equal(a, b)
 
 
+def test_four_bit_samples_unpack_to_the_eight_bit_result(oracle_lib):
+    """4-bit data (two channels per byte, even channel in the low nibble) gives
+    exactly what the same values given as 8-bit samples give."""
+    f1, df, nch = _band(32)
+    v = np.random.default_rng(6).integers(0, 16, (5000, nch)).astype(np.uint8)
+    packed = (v[:, 0::2] | (v[:, 1::2] << 4)).astype(np.uint8)
+    dms = [0.0, 25.0, 80.0]
+    assert np.array_equal(oracle.dedisperse(packed, f1, df, 2e-4, dms, nbits=4, nchan=nch),
+                          oracle.dedisperse(v, f1, df, 2e-4, dms))
+    with pytest.raises(ValueError):
+        oracle.dedisperse(packed[:, :3], f1, df, 2e-4, dms, nbits=4, nchan=5)
+
+
 def test_bad_arguments(oracle_lib):
     x = np.zeros((100, 8), np.uint8)
     for args in [(1400.0, 1.0, 1e-3, [-1.0]), (1400.0, 1.0, 0.0, [1.0]), (10.0, -2.0, 1e-3, [1.0]),
