@@ -296,6 +296,16 @@ def run_bank(args, tb, torch):
     plan = tb.Plan(batch_templates=args.batch, whiten_window=w.whiten_window, harm_max=w.harm_max,
                    threshold_sigma=w.sigma, fmin_hz=w.fmin_hz, lanes=lanes, ring_capacity=1 << 18,
                    tile_points=args.tile, flags=tb.TB_DELAY_SERIES if args.delay_series else 0)
+    if args.autotune:
+        from paper_2112_11991_amd import tune
+
+        lengths = sorted({int(s.size).bit_length() - 1 for s in w.series})
+        t0 = time.perf_counter()
+        tuned = tune.autotune(lengths, tsamp=w.tsamp, log=log)
+        tune.apply(plan, tuned)
+        conf["autotuned"] = {str(k): {"tile_points": v["tile_points"], "batch_templates": v["batch_templates"]}
+                             for k, v in tuned.items()}
+        conf["autotune_s"] = time.perf_counter() - t0
     sids = [plan.load_series(s, w.tsamp, flags=load_flags) for s in w.series]
     ntemp = len(w.templates)
     nitems = ntemp * len(sids)
@@ -439,6 +449,8 @@ def main():
                     help="whiten once per series (levels from its own spectrum) instead of per template")
     ap.add_argument("--delay-series", action="store_true",
                     help="Roemer delay from the App. B series (ELL7) instead of BT with a Newton solve")
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose FFT tile and templates per wave for each series length by timing them first")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="do not record per-kernel events")

@@ -132,6 +132,14 @@ tb_status tb_destroy(tb_plan_t plan);
 tb_status tb_load_series(tb_plan_t plan, const float* data, uint64_t n, double tsamp_s,
                          uint32_t flags, int32_t* series_id);
 
+/* Launch shape for series of 2^log2n samples: FFT points per workgroup
+ * (8192 or 16384; 0 = the plan's choice) and templates per wave (1..4096;
+ * 0 = the plan's choice), e.g. as chosen by an autotuner measuring each on
+ * the device.  Must be set before the plan first uses that length (a series
+ * of it loaded or searched): TB_ERR_INVALID_ARG afterwards, or for values
+ * outside those sets or log2n outside 10..max_log2n. */
+tb_status tb_set_shape(tb_plan_t plan, uint32_t log2n, uint32_t tile_points, uint32_t batch_templates);
+
 /* Birdie zapping (App. A and Sec. 5.2 name Fourier birdie zapping among the
  * per-series steps): replaces the series' list of interference intervals.
  * For every template searched on the series afterwards, the whitened power of

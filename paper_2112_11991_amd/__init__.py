@@ -85,7 +85,7 @@ EXPORTS = [
     "tb_default_config", "tb_plan", "tb_destroy", "tb_load_series", "tb_unload_series", "tb_search_templates",
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
-    "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density", "tb_dedisperse",
+    "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density", "tb_dedisperse", "tb_set_shape",
 ]
 
 
@@ -143,6 +143,7 @@ def _load():
     L.tb_set_budget.argtypes = [vp, u64]
     L.tb_distill.argtypes = [vp, u64, u32, u32, u32, vp, vp, P(u64)]
     L.tb_zap_series.argtypes = [vp, i32, vp, vp, u32]
+    L.tb_set_shape.argtypes = [vp, u32, u32, u32]
     L.tb_bank_density.argtypes = [vp, P(TbBankMetric), vp, u64, vp, P(C.c_double)]
     L.tb_dedisperse.argtypes = [vp, P(TbFilterbank), vp, u32, vp, u32, vp, P(u64), P(C.c_double)]
     for name in EXPORTS:
@@ -420,6 +421,11 @@ class Plan:
 
     def dedisperse(self, data, fch1_mhz, foff_mhz, tsamp_s, dms, out=None, nchan=None, nsamp=None, nbits=8):
         return tb_dedisperse(self.handle, data, fch1_mhz, foff_mhz, tsamp_s, dms, out, nchan, nsamp, nbits)
+
+    def set_shape(self, log2n, tile_points=0, batch_templates=0):
+        """Launch shape for series of 2^log2n samples (before that length is used)."""
+        _check(_L.tb_set_shape(C.c_void_p(self.handle), int(log2n), int(tile_points), int(batch_templates)),
+               "tb_set_shape")
 
     def zap(self, sid, intervals):
         """Birdie intervals (lo_hz, hi_hz) for the series; [] clears them."""

@@ -174,6 +174,7 @@ struct tb_plan_s {
     std::mutex mu;
     std::map<int32_t, SeriesRec> series;
     std::map<int, GeoRec> geo;     // by log2 n
+    std::map<int, std::pair<int, int>> shape;  // per log2 n: (tile points, templates per wave) set by tb_set_shape
     std::map<int64_t, Req> reqs;
     int32_t next_series = 0;
     int64_t next_req = 1;
@@ -296,6 +297,8 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     // 8192-point tiles (two workgroups per CU) up to 2^23 samples; at 2^24 they
     // would leave pass 2 with 8-column workgroups and 32-byte reads
     g.TE = p->cfg.tile_points ? (int)p->cfg.tile_points : (g.M >= ((int64_t)1 << 23) ? 16384 : 8192);
+    auto sh = p->shape.find(log2n);
+    if (sh != p->shape.end() && sh->second.first) g.TE = sh->second.first;
     const int64_t TE = std::min<int64_t>(g.TE, g.M);
     g.R = (int)std::max<int64_t>(16, g.M / g.TE);
     g.S = (int)(g.M / g.R);
@@ -344,6 +347,8 @@ void free_geometry(GeoRec& r)
 
 int default_batch(const tb_plan_t p, int64_t M)
 {
+    auto sh = p->shape.find(ilog2((uint64_t)M) + 1);
+    if (sh != p->shape.end() && sh->second.second) return sh->second.second;
     if (p->cfg.batch_templates) return (int)p->cfg.batch_templates;
     int64_t b = ((int64_t)1 << 26) / M;
     return (int)std::min<int64_t>(256, std::max<int64_t>(4, b));
@@ -875,6 +880,19 @@ tb_status tb_bank_density(tb_plan_t p, const tb_bank_metric* m, const tb_templat
     hipFree(d_pts);
     hipFree(d_out);
     return st;
+}
+
+tb_status tb_set_shape(tb_plan_t p, uint32_t log2n, uint32_t tile_points, uint32_t batch_templates)
+{
+    if (!p || log2n < 10 || log2n > p->cfg.max_log2n ||
+        (tile_points != 0 && tile_points != 8192 && tile_points != 16384) || batch_templates > 4096)
+        return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (p->geo.count((int)log2n)) return TB_ERR_INVALID_ARG;  // that length is already laid out
+    for (const auto& L : p->lanes)
+        if (L.slots.count((int)log2n)) return TB_ERR_INVALID_ARG;
+    p->shape[(int)log2n] = std::make_pair((int)tile_points, (int)batch_templates);
+    return TB_OK;
 }
 
 tb_status tb_zap_series(tb_plan_t p, int32_t sid, const double* lo_hz, const double* hi_hz, uint32_t count)
