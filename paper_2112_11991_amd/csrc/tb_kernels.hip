@@ -780,14 +780,16 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
 // 30..20 (the exponent and three mantissa bits, so that the few exponents a
 // block spans spread over many histogram bins), then 19..10 and 9..0.  The
 // block's values stay in registers (VPT per thread).  Counting uses LDS
-// atomics into two histogram copies (wave parity); thread t owns the
-// NBIN/NT consecutive bins from t NBIN/NT on, sums and clears them, and a
-// block-wide prefix sum over the threads finds the digit holding the rank.
+// atomics into one histogram (NC copies are summed; one measured fastest:
+// the smaller LDS footprint and clearing outweigh the extra contention);
+// thread t owns the NBIN/NT consecutive bins from t NBIN/NT on, sums and
+// clears them, and a block-wide prefix sum over the threads finds the digit
+// holding the rank.
 template <int VPT>
 __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size_t p_stride, int64_t M, int W,
                                                float* __restrict__ med, size_t med_stride)
 {
-    constexpr int NW = NT / 64, NC = 2, NB0 = 2048;
+    constexpr int NW = NT / 64, NC = 1, NB0 = 2048;
     __shared__ uint32_t hist[NC][NB0];
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_digit, s_rank;
