@@ -287,6 +287,32 @@ __device__ __forceinline__ constexpr int twst_offset(int NS) { return 15 * (NS -
 constexpr int TWST_RECORDS = 15 * (2 + 4 + 8 + 16);  // record tables of NS = 2..16
 __device__ __forceinline__ constexpr int twpow_offset(int NS) { return TWST_RECORDS + 16 * (NS - 32); }
 
+// Stage twiddles of a radix-16 Stockham stage of stride NS: v[r] *= W_{16 NS}^{r k}.
+template <int RAD, int NS>
+__device__ __forceinline__ void stage_twiddle(float2* v, const float2* __restrict__ twst, int k)
+{
+    if (NS > 1 && NS < 32) {
+        const float2* tw = twst + twst_offset(NS) + 15 * k;
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[r - 1]);
+    } else if (NS >= 32) {
+        const float2* T = twst + twpow_offset(NS);
+        float2 w[16];
+        w[1] = T[k];
+        w[2] = T[2 * k];
+        w[4] = T[4 * k];
+        w[8] = T[8 * k];
+        w[3] = cmul(w[1], w[2]);
+        w[5] = cmul(w[1], w[4]);
+        w[6] = cmul(w[2], w[4]);
+        w[7] = cmul(w[3], w[4]);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+#pragma unroll
+        for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], w[r]);
+    }
+}
+
 // One Stockham stage.  Element addresses are pidx(a) + pidx(b) with a < b's
 // stride (both powers of two), which equals pidx(a + b); writing them that way
 // leaves one address per butterfly and compile-time offsets for the rest.
@@ -303,26 +329,7 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
         const float2* src = lds + c * LSP + pidx(j);
 #pragma unroll
         for (int r = 0; r < RAD; ++r) v[u * RAD + r] = src[pidx(r * LR)];
-        if (NS > 1 && NS < 32) {
-            const float2* tw = twst + twst_offset(NS) + 15 * k;
-#pragma unroll
-            for (int r = 1; r < RAD; ++r) v[u * RAD + r] = cmul(v[u * RAD + r], tw[r - 1]);
-        } else if (NS >= 32) {
-            const float2* T = twst + twpow_offset(NS);
-            float2 w[16];
-            w[1] = T[k];
-            w[2] = T[2 * k];
-            w[4] = T[4 * k];
-            w[8] = T[8 * k];
-            w[3] = cmul(w[1], w[2]);
-            w[5] = cmul(w[1], w[4]);
-            w[6] = cmul(w[2], w[4]);
-            w[7] = cmul(w[3], w[4]);
-#pragma unroll
-            for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
-#pragma unroll
-            for (int r = 1; r < RAD; ++r) v[u * RAD + r] = cmul(v[u * RAD + r], w[r]);
-        }
+        stage_twiddle<RAD, NS>(v + u * RAD, twst, k);
         dft<RAD>(v + u * RAD);
     }
     __syncthreads();
@@ -337,23 +344,66 @@ __device__ __forceinline__ void fft_stage(float2* lds, const float2* __restrict_
     __syncthreads();
 }
 
-template <int L, int C, int NS>
+// Radix-16 stages of strides NS, 16 NS, ... below END.
+template <int L, int C, int NS, int END = L>
 struct Radix16Stages {
     static __device__ __forceinline__ void run(float2* lds, const float2* __restrict__ twst)
     {
         fft_stage<L, C, 16, NS>(lds, twst);
-        Radix16Stages<L, C, NS * 16>::run(lds, twst);
+        Radix16Stages<L, C, NS * 16, END>::run(lds, twst);
     }
 };
-template <int L, int C>
-struct Radix16Stages<L, C, L> {
+template <int L, int C, int END>
+struct Radix16Stages<L, C, END, END> {
     static __device__ __forceinline__ void run(float2*, const float2* __restrict__) {}
 };
+
+// Radix of the first stage of an L-point transform (the rest are radix 16).
+template <int L>
+struct FirstRadix {
+    static constexpr int value = (Log2<L>::value % 4) ? (1 << (Log2<L>::value % 4)) : 16;
+};
+
+// First stage (stride 1) from registers: the caller holds the 16 points
+// row0 + (L/16) i of column c of the tile, and the points a first-stage
+// butterfly joins (L/R0 apart) are all among them, so the butterflies run
+// before anything is written; the results go to their Stockham places
+// R0 j + r.  A barrier must separate these writes from later reads.
+template <int L>
+__device__ __forceinline__ void first_stage_from_regs(float2* col_lds, int row0, const float2 (&z)[16])
+{
+    constexpr int R0 = FirstRadix<L>::value, G = 16 / R0, RS = L / 16;
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        float2 a[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) a[r] = z[i + G * r];
+        dft<R0>(a);
+        float2* dst = col_lds + pidx((row0 + RS * i) * R0);
+#pragma unroll
+        for (int r = 0; r < R0; ++r) dst[r] = a[r];  // R0 consecutive points share one padding group
+    }
+}
+
+// Last stage (stride L/16) of a one-column tile into registers: thread t
+// reads points t + (L/16) r and leaves output t + (L/16) r in v[r], the
+// points the caller stores next, so the result never returns to LDS.
+template <int L>
+__device__ __forceinline__ void last_stage_to_regs(const float2* lds, const float2* __restrict__ twst, float2 (&v)[16])
+{
+    constexpr int NS = L / 16;
+    const int k = threadIdx.x;
+    const float2* src = lds + pidx(k);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = src[pidx(r * NS)];
+    stage_twiddle<16, NS>(v, twst, k);
+    dft<16>(v);
+}
 
 template <int L, int C>
 __device__ __forceinline__ void fft_tile(float2* lds, const float2* __restrict__ twst)
 {
-    constexpr int LG = Log2<L>::value, R0 = (LG % 4) ? (1 << (LG % 4)) : 16;
+    constexpr int R0 = FirstRadix<L>::value;
     static_assert(L / 16 <= TWST_NS_MAX, "stage twiddle table too short");
     fft_stage<L, C, R0, 1>(lds, twst);
     Radix16Stages<L, C, R0>::run(lds, twst);
@@ -587,6 +637,7 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
     const uint32_t n32 = (uint32_t)n;
 
     const int shift = pok[blockIdx.y];  // log2 points per polynomial chunk, 0 = exact solve
+    float2 zv[16];  // points row0 + RS i of column c
     if (shift) {
         // Sample indices fit in 32 bits: n <= 2^24 and the host bounds the delay.
         // The template's T chunk polynomials are parked in the (not yet used)
@@ -620,15 +671,20 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
                 src_out[j + 1] = i1;
             }
         }
-        __syncthreads();
-        float2* dst = lds + c * LSP + pidx(row0);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) dst[pidx(RS * i)] = make_float2(v[2 * i], v[2 * i + 1]);
+        for (int i = 0; i < 16; ++i) zv[i] = make_float2(v[2 * i], v[2 * i + 1]);
     } else {
+        // the exact gather fills the tile in natural order; each thread
+        // takes back its own points
         gather_exact<S, C1>(x, (int)n32, c0, R, lgR, tsamp, tm + blockIdx.y, lds, src_out);
+        __syncthreads();
+        const float2* own = lds + c * LSP + pidx(row0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) zv[i] = own[pidx(RS * i)];
     }
+    __syncthreads();  // the polynomials (or the exact gather's tile) are no longer read
+    first_stage_from_regs<S>(lds + c * LSP, row0, zv);
     __syncthreads();
-    fft_tile<S, C1>(lds, twst);
 
     // W_M^{(c0+c) k2} for k2 = row0 + RS i: start value times W_M^{(c0+c) RS}
     // per step (a recurrence of at most 15 products).
@@ -636,11 +692,24 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
     const uint32_t col = (uint32_t)(c0 + c);
     float2 w = twiddle2(twM_lo, twM_hi, col * (uint32_t)row0);
     const float2 z = twiddle2(twM_lo, twM_hi, col * (uint32_t)RS);
-    const float2* src = lds + c * LSP + pidx(row0);
+    if constexpr (C1 == 1) {
+        // the last stage leaves each thread exactly the points it stores
+        Radix16Stages<S, 1, FirstRadix<S>::value, S / 16>::run(lds, twst);
+        float2 y[16];
+        last_stage_to_regs<S>(lds, twst, y);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        out[i * T] = cmul(src[pidx(RS * i)], w);
-        w = cmul(w, z);
+        for (int i = 0; i < 16; ++i) {
+            out[i * T] = cmul(y[i], w);
+            w = cmul(w, z);
+        }
+    } else {
+        Radix16Stages<S, C1, FirstRadix<S>::value>::run(lds, twst);
+        const float2* src = lds + c * LSP + pidx(row0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            out[i * T] = cmul(src[pidx(RS * i)], w);
+            w = cmul(w, z);
+        }
     }
 }
 
@@ -690,21 +759,18 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
     const int a = g * D + (q < D ? q : q - D);
     const int col = q < D ? a : (a == 0 ? S / 2 : S - a);
 
+    float2 v[16];
     if (one_column) {
-        // element i: block w = k1t + RK i, column col
+        // element i: block w = k1t + RK i, column col (the first stage runs
+        // on these registers below)
         const uint32_t off0 = ((((uint32_t)k1t << lgS) + (uint32_t)col) << 3);
         const uint32_t step = (uint32_t)RK << (lgS + 3);
-        float2 v[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i)
             v[i] = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(Ys) + (off0 + step * (uint32_t)i));
-        float2* dst = lds + q * LSP + pidx(k1t);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) dst[pidx(RK * i)] = v[i];
     } else {
         // element e = (w, q, c): block w of pass 1, slot q, column c (C1 = 2^lgC1)
         const int cmask = (1 << lgC1) - 1;
-        float2 v[16];
         int laddr[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -730,8 +796,14 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
 #pragma unroll
         for (int i = 0; i < 16; ++i) fv[i] = 1.0f;
     }
-    __syncthreads();
-    fft_tile<R, D2>(lds, twst);
+    if (one_column) {
+        first_stage_from_regs<R>(lds + q * LSP, k1t, v);
+        __syncthreads();
+        Radix16Stages<R, D2, FirstRadix<R>::value>::run(lds, twst);
+    } else {
+        __syncthreads();
+        fft_tile<R, D2>(lds, twst);
+    }
 
     // Thread t emits slot q at k1 = k1t + RK i.  The split twiddle
     // W_2M^{col + S k1} advances by W_2M^{S RK} = W_32 per step.
