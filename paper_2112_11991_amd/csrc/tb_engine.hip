@@ -304,6 +304,9 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     g.S = (int)(g.M / g.R);
     g.C1 = (int)(TE / g.S);
     g.lgR = ilog2((uint64_t)g.R);
+    // rows of 2R samples: enough for a delay swing of n/8 samples, at most
+    // 2^PAD_REACH_LOG2, plus two for rounding
+    g.P = (int)(std::min<int64_t>(g.n / 8, (int64_t)1 << PAD_REACH_LOG2) / (2 * g.R)) + 2;
     g.D2 = (int)(TE / g.R);
     g.W = (int)p->cfg.whiten_window;
     g.nblk = (int)((g.M + g.W - 1) / g.W);
@@ -706,7 +709,7 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
     SeriesRec r;
     r.n = (int64_t)n;
     r.tsamp = tsamp;
-    const size_t series_bytes = sizeof(float) * (n + SERIES_PAD);
+    const size_t series_bytes = sizeof(float) * series_floats(*g);
     const size_t fac_floats = ((size_t)g->M + 1 + 63) & ~(size_t)63;
     r.bytes = series_bytes + (once ? sizeof(float) * (fac_floats + (size_t)g->nblk) : 0);
     if ((st = reserve(p, r.bytes))) return st;
@@ -737,8 +740,8 @@ tb_status tb_load_series(tb_plan_t p, const float* data, uint64_t n, double tsam
         src = staging;
     }
     if (e == hipSuccess) e = launch_mean_subtract(src, staging + n, r.n, p->d_partial, p->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(r.d, 0, series_bytes, p->stream);  // the zero rows
     if (e == hipSuccess) e = launch_tile_series(*g, staging + n, r.d, p->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(r.d + n, 0, sizeof(float) * SERIES_PAD, p->stream);
     if (e == hipSuccess && once) {
         // tau = 0: the demodulation reads every sample where it is
         static const tb_template still = {1.0, 0.0, 0.0, 0.0, 0.0};

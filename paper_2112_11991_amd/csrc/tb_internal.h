@@ -61,6 +61,7 @@ struct Geometry {
     int64_t n = 0, M = 0;
     int TE = 0;
     int S = 0, R = 0, C1 = 0, D2 = 0, lgR = 0;
+    int P = 0;             // zero rows before and after every pass-1 column block of a resident series
     int W = 0;             // whitening window (bins per median block)
     int nblk = 0;          // whitening blocks
     int htile = 0;         // harmonic-sum output bins per workgroup
@@ -73,11 +74,19 @@ struct Geometry {
 
 constexpr int TW_LO_BITS = 10;
 constexpr int TWST_NS_MAX = 1024;           // largest stage stride (16384-point transforms)
-constexpr int SERIES_PAD = 64;              // zero samples after a resident series
+constexpr int PAD_REACH_LOG2 = 20;          // largest delay swing (samples) the zero rows of a series cover
 
-// Fourth-order expansion of the sample delay around sample jmid (one per
-// chunk of 16 or 8 pass-1 tile points), 48 bytes so that records stay 16-B
-// aligned.
+// Floats of a resident series: R columns of S complex points in blocks of
+// C1, each block with P zero rows after it and P before the first.
+inline size_t series_floats(const Geometry& g)
+{
+    return 2 * ((size_t)g.R * (size_t)(g.S + g.P) + (size_t)g.P * (size_t)g.C1);
+}
+
+// Fourth-order expansion of the sample delay around the middle sample of a
+// chunk of 16 or 8 pass-1 tile points, 48 bytes so that records stay 16-B
+// aligned.  jmid is that sample plus 2PR, in the shifted indices the pass-1
+// gather works with (P zero rows of 2R samples precede a resident series).
 struct ChunkPoly {
     double c0, c1, c2, c3, c4;
     int32_t jmid, pad;

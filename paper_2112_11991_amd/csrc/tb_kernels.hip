@@ -511,49 +511,66 @@ __device__ __forceinline__ int64_t source_from_poly(const DelayPoly& d, int64_t 
 // ------------------------------------------------------------------------
 // Resident series layout.  The mean-removed series is stored as complex
 // pairs z_m = (x_2m, x_2m+1) in the tile order of pass 1: point m = n1 + R s
-// (n1 < R, s < S) sits at ((n1 / C1) S + s) C1 + n1 % C1.  Pass-1 workgroup w
-// reads columns n1 in [w C1, (w+1) C1) down all rows s; a delayed read lands
-// in the same or a neighbouring column a few rows away, so its loads stay
-// contiguous instead of touching one cache line per sample.  SERIES_PAD zero
-// samples follow the n samples: a read outside the series is sent there.
-template <int S, int C1>
-__device__ __forceinline__ uint32_t tiled_index(uint32_t i, int lgR)
+// (n1 < R, s < S) sits at ((n1 / C1) (S + P) + P + s) C1 + n1 % C1, so each
+// block of C1 columns runs down all S rows and is followed by P zero rows,
+// and P zero rows precede the first block.  Pass-1 workgroup w reads columns
+// n1 in [w C1, (w+1) C1) down all rows; a delayed read lands in the same or
+// a neighbouring column a few rows away, so consecutive lanes (consecutive
+// rows) read neighbouring pairs, and the two samples of a point usually share
+// one pair.  A sample index outside [0, n) by less than P - 1 rows (2R
+// samples each) falls on zero rows, so the gather needs no range test: it
+// works on i' = i + 2PR >= 0, which has the same column n1 and parity as i and
+// row s + P.
+__device__ __forceinline__ uint32_t bit_insert_low(uint32_t hi, uint32_t lo)
 {
-    constexpr int LS = Log2<S>::value, LC = Log2<C1>::value;
-    const uint32_t n1 = (i >> 1) & ((1u << lgR) - 1), s = i >> (lgR + 1);
-    const uint32_t pt = ((n1 >> LC) << (LS + LC)) | (s << LC) | (n1 & (C1 - 1));
-    return (pt << 1) | (i & 1);
+    uint32_t r;  // (hi & ~1) | (lo & 1)
+    asm("v_bfi_b32 %0, 1, %1, %2" : "=v"(r) : "v"(lo), "v"(hi));
+    return r;
 }
 
-// Sample i of the resident series, or one of the zero samples after it when
-// i is outside [0, n).  The index is computed unconditionally and then
-// selected, so that the gather stays one basic block the scheduler can
-// reorder; the load uses a 32-bit byte offset from the series base.
-template <int S, int C1>
-__device__ __forceinline__ float load_sample(const float* __restrict__ x, int i, uint32_t n, int lgR)
+template <int C1>
+__device__ __forceinline__ uint32_t padded_index(uint32_t ip, int lgR, uint32_t SP)
 {
-    uint32_t t = tiled_index<S, C1>((uint32_t)i, lgR);
-    asm volatile("" : "+v"(t));
-    const uint32_t a = (uint32_t)i < n ? t : n;
+    constexpr int LC = Log2<C1>::value;
+    const uint32_t n1 = __builtin_amdgcn_ubfe(ip, 1u, (uint32_t)lgR);
+    if constexpr (C1 == 1) {
+        // float offset 2 (n1 (S + P) + s + P) + parity; i' >> lgR is
+        // 2 (s + P) plus one bit of n1, replaced by the parity
+        return __umul24(n1, 2 * SP) + bit_insert_low(ip >> lgR, ip);
+    } else {
+        const uint32_t blk = __umul24(n1 >> LC, SP) + (ip >> (lgR + 1));
+        return (((blk << LC) | (n1 & (C1 - 1))) << 1) | (ip & 1u);
+    }
+}
+
+// Sample at shifted index i' (see above; zero outside the series); the load
+// uses a 32-bit byte offset from the series base.
+template <int C1>
+__device__ __forceinline__ float load_sample(const float* __restrict__ x, int ip, int lgR, uint32_t SP)
+{
+    const uint32_t a = padded_index<C1>((uint32_t)ip, lgR, SP);
     return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(x) + (a << 2));
 }
 
 // Pass-1 gather for templates whose delay polynomial would not meet the
 // accuracy bound: Kepler solve at every sample, written straight to the tile.
 // Kept out of line so that its FP64 code does not crowd the common path.
+// Any delay: indices outside the series read element 0, a zero row.
 template <int S, int C1>
 __device__ __attribute__((noinline)) void gather_exact(const float* __restrict__ x, int n, int c0, int R, int lgR,
-                                                       double tsamp, const TmplDev* __restrict__ tp, float2* lds,
-                                                       int32_t* __restrict__ src_out)
+                                                       int P, double tsamp, const TmplDev* __restrict__ tp,
+                                                       float2* lds, int32_t* __restrict__ src_out)
 {
     constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1;
     const TmplDev& p = *tp;
+    const uint32_t SP = (uint32_t)(S + P);
+    const int jsh = 2 * P * R;
 #pragma unroll 1
     for (int e = threadIdx.x; e < C1 * S; e += T) {
         const int j = 2 * (c0 + (e % C1) + R * (e / C1));
         const int i0 = (int)source_index(p, j, tsamp), i1 = (int)source_index(p, j + 1, tsamp);
-        const uint32_t a0 = (unsigned)i0 < (unsigned)n ? tiled_index<S, C1>(i0, lgR) : (uint32_t)n;
-        const uint32_t a1 = (unsigned)i1 < (unsigned)n ? tiled_index<S, C1>(i1, lgR) : (uint32_t)n;
+        const uint32_t a0 = (unsigned)i0 < (unsigned)n ? padded_index<C1>(i0 + jsh, lgR, SP) : 0u;
+        const uint32_t a1 = (unsigned)i1 < (unsigned)n ? padded_index<C1>(i1 + jsh, lgR, SP) : 0u;
         if (src_out) {
             src_out[j] = i0;
             src_out[j + 1] = i1;
@@ -562,12 +579,14 @@ __device__ __attribute__((noinline)) void gather_exact(const float* __restrict__
     }
 }
 
+// Natural order -> the padded tile order above (the zero rows are cleared
+// beforehand).
 __global__ __launch_bounds__(NT) void k_tile_series(const float* __restrict__ in, float* __restrict__ out, int64_t M,
-                                                    int lgR, int S, int C1)
+                                                    int lgR, int S, int C1, int P)
 {
     for (int64_t m = (int64_t)blockIdx.x * NT + threadIdx.x; m < M; m += (int64_t)gridDim.x * NT) {
         const int64_t n1 = m & ((1ll << lgR) - 1), s = m >> lgR;
-        const int64_t d = ((n1 / C1) * S + s) * C1 + (n1 % C1);
+        const int64_t d = ((n1 / C1) * (S + P) + P + s) * C1 + (n1 % C1);
         reinterpret_cast<float2*>(out)[d] = reinterpret_cast<const float2*>(in)[m];
     }
 }
@@ -583,8 +602,8 @@ __global__ __launch_bounds__(NT) void k_tile_series(const float* __restrict__ in
 // same samples, so one word per template gives log2 of the chunk size used
 // (4 or 3), or 0 for the exact per-sample solve.
 __global__ __launch_bounds__(NT) void k_chunk_polys(const TmplDev* __restrict__ tm, double tsamp, int R, int C1,
-                                                    int npts, ChunkPoly* __restrict__ polys, size_t poly_stride,
-                                                    int32_t* __restrict__ pok)
+                                                    int P, int64_t n, int npts, ChunkPoly* __restrict__ polys,
+                                                    size_t poly_stride, int32_t* __restrict__ pok)
 {
     const int g = (int)(blockIdx.x * NT + threadIdx.x);
     const TmplDev p = tm[blockIdx.y];
@@ -593,7 +612,24 @@ __global__ __launch_bounds__(NT) void k_chunk_polys(const TmplDev* __restrict__ 
         const int lo = jof(0), hi = jof(len - 1) + 1, mid = lo + (hi - lo) / 2;
         return (double)(hi - mid) + 2.0 * (double)(R - C1);
     };
-    const int shift = poly_ok(p, tsamp, reach(16)) ? 4 : poly_ok(p, tsamp, reach(8)) ? 3 : 0;
+    // Delay swing: delta is taken relative to sample 0, so over the n samples
+    // |delta| <= tau min(2 max|F|, Omega n tsamp max|dF/dM|) / tsamp; for the
+    // BT delay max|F| <= 1 + e and max|dF/dM| <= 1 / (1 - e), for the series
+    // the sums of |coefficient| and k |coefficient|.  A swing that could leave
+    // the zero rows of the resident series takes the exact path, which tests
+    // every index.
+    double fmax = 1.0 + p.ecc, dfmax = 1.0 / (1.0 - p.ecc);
+    if (p.model) {
+        fmax = fabs(p.ca[0] - p.ecc * p.sinw);
+        dfmax = 0.0;
+        for (int k = 1; k < 8; ++k) {
+            fmax += fabs(p.ca[k]) + fabs(p.sb[k]);
+            dfmax += k * (fabs(p.ca[k]) + fabs(p.sb[k]));
+        }
+    }
+    const double swing = p.tau * fmin(2.0 * fmax, p.omega * (double)n * tsamp * dfmax) / tsamp;
+    const bool in_pad = swing + 1.0 <= 2.0 * (double)R * (double)(P - 1);
+    const int shift = !in_pad ? 0 : poly_ok(p, tsamp, reach(16)) ? 4 : poly_ok(p, tsamp, reach(8)) ? 3 : 0;
     if (g == 0) pok[blockIdx.y] = shift;
     if (shift == 0 || g >= (npts >> shift)) return;
     const int len = 1 << shift;
@@ -605,7 +641,7 @@ __global__ __launch_bounds__(NT) void k_chunk_polys(const TmplDev* __restrict__ 
     c.c2 = d.c2;
     c.c3 = d.c3;
     c.c4 = d.c4;
-    c.jmid = mid;
+    c.jmid = mid + 2 * P * R;  // in the shifted indices of the gather
     c.pad = 0;
     polys[blockIdx.y * poly_stride + g] = c;
 }
@@ -620,7 +656,7 @@ __global__ __launch_bounds__(NT) void k_chunk_polys(const TmplDev* __restrict__ 
 // t / C1 + (S/16) i, so a wave's loads are consecutive rows.
 template <int S, int C1>
 __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict__ x, int64_t n, int R, int lgR,
-                                                      double tsamp, const TmplDev* __restrict__ tm,
+                                                      int P, double tsamp, const TmplDev* __restrict__ tm,
                                                       const ChunkPoly* __restrict__ polys, size_t poly_stride,
                                                       const int32_t* __restrict__ pok,
                                                       float2* __restrict__ Y, size_t y_stride,
@@ -631,6 +667,7 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
     constexpr int T = C1 * S / 16, LSP = S + S / 16 + 1, RS = S / 16;
     __shared__ __align__(16) float2 lds[C1 * LSP];
     static_assert(sizeof(ChunkPoly) * 2 * T <= sizeof(float2) * C1 * LSP, "polynomials must fit in the tile");
+    static_assert(T % 16 == 0, "chunks of 16 points must not straddle a thread's rows");
     const int tile = xcd_remap(blockIdx.x, R / C1);
     const int c0 = tile * C1;
     const int c = (int)threadIdx.x % C1, row0 = (int)threadIdx.x / C1;
@@ -639,36 +676,45 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
     const int shift = pok[blockIdx.y];  // log2 points per polynomial chunk, 0 = exact solve
     float2 zv[16];  // points row0 + RS i of column c
     if (shift) {
-        // Sample indices fit in 32 bits: n <= 2^24 and the host bounds the delay.
+        // Sample indices fit in 32 bits: n <= 2^24 and the host bounds the delay;
+        // this path's delays stay within the zero rows (checked per template).
         // The template's T chunk polynomials are parked in the (not yet used)
         // tile memory, so that their reads wait on LDS only and the series
         // loads of earlier points stay in flight.
         ChunkPoly* cp = reinterpret_cast<ChunkPoly*>(lds);
         for (int c = (int)threadIdx.x; c < (C1 * S) >> shift; c += T) cp[c] = polys[blockIdx.y * poly_stride + c];
         __syncthreads();
-        auto sources = [&](int i, int& j, int& i0, int& i1) {
-            const ChunkPoly d = cp[((int)threadIdx.x + i * T) >> shift];
-            j = 2 * (c0 + c + R * (row0 + RS * i));
-            const double u = (double)(j - d.jmid), u1 = u + 1.0;
+        // Indices are shifted by P rows (jsh samples), the chunk centres too.
+        // T is a multiple of 16, so point t + T i lies in chunk
+        // (t >> shift) + i (T >> shift).
+        const int jsh = 2 * P * R;
+        const int jbase = 2 * (c0 + c + R * row0) + jsh, jstep = 2 * R * RS;
+        const ChunkPoly* cpt = cp + ((int)threadIdx.x >> shift);
+        const int cstep = T >> shift;
+        auto sources = [&](int i, int& jp, int& ip0, int& ip1) {
+            const ChunkPoly d = cpt[i * cstep];
+            jp = jbase + i * jstep;
+            const double u = (double)(jp - d.jmid), u1 = u + 1.0;
             const double d0 = d.c0 + u * (d.c1 + u * (d.c2 + u * (d.c3 + u * d.c4)));
             const double d1 = d.c0 + u1 * (d.c1 + u1 * (d.c2 + u1 * (d.c3 + u1 * d.c4)));
-            i0 = j - rint_i32(d0);
-            i1 = j + 1 - rint_i32(d1);
+            ip0 = jp - rint_i32(d0);
+            ip1 = jp + 1 - rint_i32(d1);
         };
+        const uint32_t SP = (uint32_t)(S + P);
         float v[32];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            int j, i0, i1;
-            sources(i, j, i0, i1);
-            v[2 * i] = load_sample<S, C1>(x, i0, n32, lgR);
-            v[2 * i + 1] = load_sample<S, C1>(x, i1, n32, lgR);
+            int jp, ip0, ip1;
+            sources(i, jp, ip0, ip1);
+            v[2 * i] = load_sample<C1>(x, ip0, lgR, SP);
+            v[2 * i + 1] = load_sample<C1>(x, ip1, lgR, SP);
         }
         if (src_out) {
             for (int i = 0; i < 16; ++i) {
-                int j, i0, i1;
-                sources(i, j, i0, i1);
-                src_out[j] = i0;
-                src_out[j + 1] = i1;
+                int jp, ip0, ip1;
+                sources(i, jp, ip0, ip1);
+                src_out[jp - jsh] = ip0 - jsh;
+                src_out[jp - jsh + 1] = ip1 - jsh;
             }
         }
 #pragma unroll
@@ -676,7 +722,7 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
     } else {
         // the exact gather fills the tile in natural order; each thread
         // takes back its own points
-        gather_exact<S, C1>(x, (int)n32, c0, R, lgR, tsamp, tm + blockIdx.y, lds, src_out);
+        gather_exact<S, C1>(x, (int)n32, c0, R, lgR, P, tsamp, tm + blockIdx.y, lds, src_out);
         __syncthreads();
         const float2* own = lds + c * LSP + pidx(row0);
 #pragma unroll
@@ -1178,7 +1224,7 @@ hipError_t fft1_launch(const Geometry& g, const float* x, double tsamp, const Tm
                        const Slots& ws, int32_t* src_out, hipStream_t s)
 {
     dim3 grid(g.R / C1, nslots);
-    hipLaunchKernelGGL((k_fft1<S, C1>), grid, dim3(C1 * S / 16), 0, s, x, g.n, g.R, g.lgR, tsamp, tm, ws.poly,
+    hipLaunchKernelGGL((k_fft1<S, C1>), grid, dim3(C1 * S / 16), 0, s, x, g.n, g.R, g.lgR, g.P, tsamp, tm, ws.poly,
                        ws.poly_stride, ws.pok, ws.Y, ws.y_stride, g.twst, g.twM_lo, g.twM_hi, src_out);
     return hipGetLastError();
 }
@@ -1263,7 +1309,7 @@ hipError_t launch_tile_series(const Geometry& g, const float* in, float* out, hi
 {
     int64_t blocks = (g.M + NT - 1) / NT;
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_tile_series, dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.M, g.lgR, g.S, g.C1);
+    hipLaunchKernelGGL(k_tile_series, dim3((unsigned)blocks), dim3(NT), 0, s, in, out, g.M, g.lgR, g.S, g.C1, g.P);
     return hipGetLastError();
 }
 
@@ -1304,7 +1350,7 @@ hipError_t launch_power(const Geometry& g, const float* x, double tsamp, const T
     if ((e = mark(marks, K_POLY, s)) != hipSuccess) return e;
     const int npts = (int)std::min<int64_t>(g.TE, g.M), nchunk = npts / 8;
     hipLaunchKernelGGL(k_chunk_polys, dim3((nchunk + NT - 1) / NT, nslots), dim3(NT), 0, s, tmw, tsamp, g.R, g.C1,
-                       npts, ws.poly, ws.poly_stride, ws.pok);
+                       g.P, g.n, npts, ws.poly, ws.poly_stride, ws.pok);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int q0 = 0; q0 < nslots; q0 += ws.BY) {
         const int nq = std::min(ws.BY, nslots - q0);

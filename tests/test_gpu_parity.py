@@ -238,14 +238,22 @@ def test_argument_errors(tb):
 
 
 def test_hbm_budget_admission(tb):
+    """A series is admitted while the budget holds its bytes (samples plus the
+    zero rows around its columns, 4n to 5n) and refused otherwise."""
     n, ts = 1 << 16, 64e-6
     x = _series(n, ts, seed=15)
-    with tb.Plan(hbm_budget_bytes=int(2.5 * 4 * n)) as plan:
+    with tb.Plan() as plan:
+        plan.load_series(x, ts)  # lays out the length too
+        h1 = plan.memory()[0]
         plan.load_series(x, ts)
-        plan.load_series(x, ts)
+        per = plan.memory()[0] - h1
+        assert 4 * n <= per <= 5 * n
+        plan.set_budget(plan.memory()[0] + per - 1)
         with pytest.raises(tb.TbError) as e:
             plan.load_series(x, ts)
         assert e.value.status == tb.TB_ERR_BUDGET
+        plan.set_budget(plan.memory()[0] + per)
+        plan.load_series(x, ts)
 
 
 def test_device_resident_input(tb):
