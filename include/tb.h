@@ -119,7 +119,9 @@ tb_status tb_destroy(tb_plan_t plan);
 /* Copies a dedispersed series S_i, i = 0..n-1 at times i*tsamp (App. A.1),
  * into plan memory (from host, or device-to-device on the plan stream for
  * TB_MEM_DEVICE) and removes its mean in double precision.  Returns the new
- * id in *series_id.  TB_ERR_BUDGET if it does not fit the HBM budget.
+ * id in *series_id.  TB_ERR_BUDGET if it does not fit the HBM budget.  A
+ * series occupies 4n bytes plus about 4 min(n/8, 2^20) bytes of zero padding
+ * that reads before or after it land on (counted by tb_memory).
  *
  * With TB_SERIES_WHITENING the Fourier de-reddening (App. A, Sec. 5.2) is done
  * once for the series instead of once per template: the block medians of the

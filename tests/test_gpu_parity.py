@@ -60,6 +60,10 @@ CASES = [
     (19, 64e-6, 2048, (3000.0, 2.0, 0.1, 0.0, 0.0)),
     # a short orbit whose delay needs the 8-point polynomial chunks at this size
     (21, 64e-6, 4096, (380.0, 1.5, 2.0, 0.05, 1.0)),
+    # a delay swing (about 12,000 samples) beyond the zero rows around the
+    # resident series (8,223 samples at 2^16): the exact per-sample path,
+    # though the polynomials would be accurate
+    (16, 64e-6, 4096, (100.0, 3.0, 0.5, 0.0, 0.0)),
 ]
 
 
