@@ -5,16 +5,16 @@ selection of templates with density proportional to sqrt|gamma|.
 TEST INFRASTRUCTURE ONLY (part of the oracle): plain FP64 numpy, written from
 the paper's definitions; the product library never imports it.
 
-- Phase (Sec. 2.6, eq. "dimensionless phase"): Phi = chi Phi~ with
+- Phase (Sec. 2.6, the equation of the dimensionless phase): Phi = chi Phi~ with
   chi = 2 pi f_max T and Phi~ = kappa u + X cos E + Y sqrt(1-e^2) sin E,
   u = t/T in [0, 1], X = tau sin(psi)/T, Y = tau cos(psi)/T, M = Omega' u + alpha,
   Omega' = Omega T, E - e sin E = M.  Circular orbits: Phi~ = kappa u +
   tau' sin(Omega' u + alpha), tau' = tau/T (psi merges into alpha).
-- Metric (Sec. 2.2, eq. "metric tensor"): g_ab = <d_a Phi d_b Phi> - <d_a Phi><d_b Phi>,
+- Metric (Sec. 2.2, the equation of the metric tensor): g_ab = <d_a Phi d_b Phi> - <d_a Phi><d_b Phi>,
   time averages over u; projected to constant frequency (Sec. 2.5):
   gamma_ab = g_ab - g_ka g_kb / g_kk.  Averages by Gauss-Legendre quadrature.
-- Volume and count (Sec. 2.3, eqs. "volume", "total templates", "number
-  templates"): V = int sqrt(det gamma) d^n lambda, C_n = pi^(n/2)/Gamma(n/2+1),
+- Volume and count (Sec. 2.3, the equations of the proper volume, the total
+  template count and the random-template count): V = int sqrt(det gamma) d^n lambda, C_n = pi^(n/2)/Gamma(n/2+1),
   N_R = ln(1 - eta) / ln(1 - m^(n/2) C_n / V).
 - Coordinates of the bank (the sampling coordinates): circular
   (P_orb, tau, alpha), elliptical (P_orb, tau, alpha, e, psi).  The density in

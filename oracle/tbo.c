@@ -50,7 +50,7 @@ double tbo_kepler(double M, double e, int32_t* iters)
     return E;
 }
 
-/* Roemer delay of the BT model (App. A.1, eq. "romer delay bt"):
+/* Roemer delay of the BT model (App. A.1, the equation of the BT Roemer delay):
  *   Delta = tau [ (cos E - e) sin psi + sqrt(1 - e^2) sin E cos psi ],
  * with the mean anomaly M = Omega t + alpha of the Kepler equation in Sec. 2.1
  * (Omega = 2 pi / P_orb, the mean angular velocity). */

@@ -22,7 +22,7 @@
  *                             "romer delay bt" (BT model)
  *   O4 nearest-neighbour index App. A.1 and Algorithm 1 (zero offset at t=0)
  *   O5 DFT .................. Sec. 2.4 (uniform spin-frequency grid by FFT)
- *   O6 power ................ Sec. 2.1 eq. "power detection statistic"
+ *   O6 power ................ Sec. 2.1, equation of the power statistic
  *   O7 whitening ............ "Fourier de-reddening", Sec. 5.2 / App. A
  *                             (method not given by the paper: block medians,
  *                             linear interpolation, normalised so that noise
