@@ -678,9 +678,10 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
     if (shift) {
         // Sample indices fit in 32 bits: n <= 2^24 and the host bounds the delay;
         // this path's delays stay within the zero rows (checked per template).
-        // The template's T chunk polynomials are parked in the (not yet used)
-        // tile memory, so that their reads wait on LDS only and the series
-        // loads of earlier points stay in flight.
+        // The template's chunk polynomials (T of them for 16-point chunks, 2T
+        // for 8-point ones) are parked in the (not yet used) tile memory, so
+        // that their reads wait on LDS only and the series loads of earlier
+        // points stay in flight.
         ChunkPoly* cp = reinterpret_cast<ChunkPoly*>(lds);
         for (int c = (int)threadIdx.x; c < (C1 * S) >> shift; c += T) cp[c] = polys[blockIdx.y * poly_stride + c];
         __syncthreads();
