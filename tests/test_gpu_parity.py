@@ -98,6 +98,24 @@ def test_stages_match_oracle_16384_point_tiles(tb, lg, ts, W, tm):
         _say("  tie-exempt indices:", ex)
 
 
+@pytest.mark.parametrize("kind", ["impulse", "zeros"])
+def test_crowded_median_digits(tb, kind):
+    """Spectra whose whitening blocks hold thousands of (nearly) equal powers:
+    a unit impulse (|X_k|^2 = 1 for k >= 1 up to FP32 rounding, so the
+    values of a block share the median's leading bits) and an all-zero series
+    (every power exactly 0).  The radix selection of the block medians meets
+    crowded digits in every pass; every stage still matches the oracle."""
+    n, ts, W = 1 << 16, 64e-6, 4096
+    x = np.zeros(n, np.float32)
+    if kind == "impulse":
+        x[12345] = 1.0
+    tm = (3600.0, 0.0, 0.0, 0.0, 0.0)
+    _say("crowded median digits: %s" % kind)
+    with tb.Plan(whiten_window=W) as plan:
+        sid = plan.load_series(x, ts)
+        _stage_check(tb, plan, sid, x, n, ts, tm, W)
+
+
 def test_zero_orbit_is_identity_on_gpu(tb):
     n, ts = 1 << 16, 64e-6
     x = _series(n, ts, seed=5)
