@@ -457,8 +457,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-template-per-launch comparison")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; --gpus %d is not supported (multi-GPU sharding is a design "
-              "note only)" % args.gpus, file=sys.stderr)
+        print("bench.py: the search runs on one GPU; --gpus %d is not supported (sharding the bank over GPUs is "
+              "described, not implemented)" % args.gpus, file=sys.stderr)
         return 2
 
     import torch
