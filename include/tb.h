@@ -109,11 +109,17 @@ typedef struct {
 void tb_default_config(tb_config* cfg);
 
 /* Creates a plan: checks cfg, makes device cfg->device current, creates or
- * adopts the stream.  Returns TB_ERR_INVALID_ARG for a bad cfg, TB_ERR_DEVICE
- * if the device cannot be used. */
+ * adopts the stream, and fixes the search parameters every request uses: the
+ * number of harmonics summed and the false-alarm threshold of Sec. 2.1
+ * (harmonic sums up to 16 and the search set-up of Sec. 5.2), the whitening
+ * window of the Fourier de-reddening (Sec. 5.2, App. A) and the searched
+ * frequency band (the uniform frequency grid of Sec. 2.4).  Returns
+ * TB_ERR_INVALID_ARG for a bad cfg, TB_ERR_DEVICE if the device cannot be
+ * used. */
 tb_status tb_plan(const tb_config* cfg, tb_plan_t* out);
 
-/* Waits for the plan's work, frees everything it owns.  NULL is a no-op. */
+/* Waits for the plan's work, frees everything it owns.  NULL is a no-op.
+ * Resource management only: the paper defines no such step. */
 tb_status tb_destroy(tb_plan_t plan);
 
 /* Copies a dedispersed series S_i, i = 0..n-1 at times i*tsamp (App. A.1),
@@ -168,10 +174,17 @@ tb_status tb_unload_series(tb_plan_t plan, int32_t series_id);
 tb_status tb_search_templates(tb_plan_t plan, int32_t series_id, const tb_template* t,
                               uint32_t count, uint32_t first_template_id, int64_t* request_id);
 
-/* TB_OK once the request's device work has finished, TB_ERR_NOT_READY before. */
+/* TB_OK once the request's device work has finished (its threshold step of
+ * Sec. 2.1 and peak detection of App. A included), TB_ERR_NOT_READY before;
+ * TB_ERR_UNKNOWN_ID for an unknown request, TB_ERR_DEVICE if the device
+ * reported an error. */
 tb_status tb_poll(tb_plan_t plan, int64_t request_id);
 
-/* Copies up to capacity candidates of a request into out (host), sorted by
+/* The candidates of a request: every bin of every harmonic fold whose sum
+ * exceeds the fold's false-alarm threshold (the threshold step of Sec. 2.1;
+ * the peak detection of App. A, read as every bin above threshold), with the
+ * Gaussian-equivalent significance and fundamental frequency of each.
+ * Copies up to capacity candidates of a request into out (host), sorted by
  * (series, template, log2_harm, bin), and the full count into *n_total
  * (out may be NULL to query the count).  blocking != 0 waits for the request;
  * otherwise TB_ERR_NOT_READY is returned while it runs.  TB_ERR_OVERFLOW if
@@ -179,7 +192,9 @@ tb_status tb_poll(tb_plan_t plan, int64_t request_id);
 tb_status tb_get_candidates(tb_plan_t plan, int64_t request_id, tb_candidate* out,
                             uint64_t capacity, uint64_t* n_total, int blocking);
 
-/* Waits for and forgets a request, freeing its device memory. */
+/* Waits for and forgets a request, freeing its device memory.  Resource
+ * management only: the paper defines no such step.  TB_ERR_UNKNOWN_ID for an
+ * unknown request. */
 tb_status tb_release(tb_plan_t plan, int64_t request_id);
 
 /* Blocks until every queued request of the plan has finished. */
@@ -193,7 +208,7 @@ tb_status tb_memory(tb_plan_t plan, uint64_t* held_bytes, uint64_t* budget_bytes
  * later allocations that would exceed the budget fail with TB_ERR_BUDGET. */
 tb_status tb_set_budget(tb_plan_t plan, uint64_t budget_bytes);
 
-/* Static description of a status. */
+/* Static description of a status (a utility; the paper defines nothing here). */
 const char* tb_strerror(tb_status status);
 
 /* Per-stage outputs of one template, for checking the stages one by one
