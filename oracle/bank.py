@@ -16,6 +16,12 @@ the paper's definitions; the product library never imports it.
 - Volume and count (Sec. 2.3, the equations of the proper volume, the total
   template count and the random-template count): V = int sqrt(det gamma) d^n lambda, C_n = pi^(n/2)/Gamma(n/2+1),
   N_R = ln(1 - eta) / ln(1 - m^(n/2) C_n / V).
+- Two routes to the projected metric: gamma_plain writes the definitions
+  out in mpmath (one point at a time); gamma_tilde gets the same numbers in
+  FP64 through the residuals of a straight-line fit in u (vectorised, for
+  Monte-Carlo volumes).  The tests pin gamma_plain by a brute-force metric
+  of the phase in the bank's own coordinates (finite differences, no
+  Jacobian) and hold gamma_tilde to gamma_plain.
 - Coordinates of the bank (the sampling coordinates): circular
   (P_orb, tau, alpha), elliptical (P_orb, tau, alpha, e, psi).  The density in
   them is sqrt(det gamma~) chi^n times the Jacobian of the dimensionless
@@ -79,9 +85,81 @@ def sqrt_det_gamma(kind, T, f_max, porb, tau, alpha, ecc=None, psi=None, nodes: 
     return np.sqrt(np.clip(det, 0.0, None)) * chi ** n
 
 
+def _derivatives_mp(kind, T, porb, tau, alpha, ecc, psi, u):
+    """d Phi~ / d(kappa, lambda) at one node u (mpmath), lambda as in
+    _derivatives: the first entry is d Phi~ / d kappa = u."""
+    mp = _mp()
+    Op = 2 * mp.pi / porb * T
+    M = Op * u + alpha
+    if kind == 0:
+        tp = tau / T
+        return [u, mp.sin(M), tp * u * mp.cos(M), tp * mp.cos(M)]
+    e = ecc
+    X, Y = tau * mp.sin(psi) / T, tau * mp.cos(psi) / T
+    E = M
+    for _ in range(200):
+        step = (E - e * mp.sin(E) - M) / (1 - e * mp.cos(E))
+        E -= step
+        if abs(step) < mp.mpf(10) ** (-mp.dps + 5):
+            break
+    sE, cE = mp.sin(E), mp.cos(E)
+    b = mp.sqrt(1 - e * e)
+    dEdM = 1 / (1 - e * cE)
+    dEde = sE / (1 - e * cE)
+    A = -X * sE + Y * b * cE
+    return [u, cE, b * sE, A * dEde - Y * e / b * sE, A * dEdM * u, A * dEdM]
+
+
+def _mp():
+    import mpmath
+
+    return mpmath.mp
+
+
+def gamma_plain(kind, T, porb, tau, alpha, ecc=0.0, psi=0.0, nodes: int = 128, dps: int = 40):
+    """The projected metric of one point written out as the paper defines it
+    (Sec. 2.2 and 2.5): g_ab = <d_a Phi~ d_b Phi~> - <d_a Phi~><d_b Phi~>
+    over the coordinates (kappa, lambda), then gamma_ab = g_ab - g_ka g_kb /
+    g_kk, in mpmath at dps digits so that short orbital arcs, where the
+    products nearly cancel, keep their digits.  Same Gauss-Legendre nodes as
+    gamma_tilde.  Returns an n x n list of mpf."""
+    mp = _mp()
+    with mp.workdps(dps):
+        x, w = np.polynomial.legendre.leggauss(nodes)
+        us = [(mp.mpf(float(v)) + 1) / 2 for v in x]
+        # weights summing to 1 exactly: the average of a constant is that
+        # constant, so constant parts of the derivatives cancel to all digits
+        ws = [mp.mpf(float(v)) for v in w]
+        tot = mp.fsum(ws)
+        ws = [v / tot for v in ws]
+        args = [mp.mpf(float(v)) for v in (T, porb, tau, alpha, ecc, psi)]
+        d = [_derivatives_mp(kind, args[0], args[1], args[2], args[3], args[4], args[5], u) for u in us]
+        k = len(d[0])
+        mean = [mp.fsum(wi * di[a] for wi, di in zip(ws, d)) for a in range(k)]
+        g = [[mp.fsum(wi * di[a] * di[b] for wi, di in zip(ws, d)) - mean[a] * mean[b] for b in range(k)]
+             for a in range(k)]
+        return [[g[a][b] - g[0][a] * g[0][b] / g[0][0] for b in range(1, k)] for a in range(1, k)]
+
+
+def density_plain(kind, T, f_max, porb, tau, alpha, ecc=0.0, psi=0.0, nodes: int = 128, dps: int = 40):
+    """The density of `density` from gamma_plain (one point, mpmath)."""
+    mp = _mp()
+    with mp.workdps(dps):
+        gam = mp.matrix(gamma_plain(kind, T, porb, tau, alpha, ecc, psi, nodes, dps))
+        n = gam.rows
+        chi = 2 * mp.pi * mp.mpf(f_max) * mp.mpf(T)
+        s = mp.sqrt(mp.det(gam)) * chi ** n
+        P, t = mp.mpf(float(porb)), mp.mpf(float(tau))
+        jac = 2 * mp.pi / P ** 2 if kind == 0 else t * 2 * mp.pi / (mp.mpf(float(T)) * P ** 2)
+        return s * jac
+
+
 def gamma_tilde(kind, T, porb, tau, alpha, ecc=None, psi=None, nodes: int = 256):
     """The frequency-projected metric of the dimensionless phase, one n x n
-    matrix per point."""
+    matrix per point, in FP64 (vectorised; the route the bulk volumes use).
+    It computes the quantity gamma_plain writes out, by another route that
+    keeps its digits for short arcs in FP64; the tests hold the two
+    together."""
     porb = np.atleast_1d(np.asarray(porb, dtype=np.float64))
     tau = np.broadcast_to(np.asarray(tau, dtype=np.float64), porb.shape)
     alpha = np.broadcast_to(np.asarray(alpha, dtype=np.float64), porb.shape)
