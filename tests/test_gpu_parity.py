@@ -295,16 +295,19 @@ def test_device_resident_input(tb):
 
 
 def test_full_size_circular_survey(tb):
-    """2^23 samples with red noise and a pulsar, in the launch configuration of
-    the benchmark (8 templates in flight): bit-exact indices and whole-spectrum
-    power parity for one template, candidate parity for three of 16."""
-    w = synth.c2_survey(n_templates=16)
+    """2^23 samples with red noise and a pulsar, in the benchmark's launch
+    configuration (the library defaults: 16 templates per wave, passes 1-2 in
+    groups of 4, 8192-point tiles): bit-exact indices and whole-spectrum power
+    parity for one template, candidate parity for all 16 templates of the
+    wave (15 of the bank and the injected orbit)."""
+    w = synth.c2_survey(n_templates=15)
+    w.templates = np.concatenate([w.templates, w.truths[0][1].as_template()])
     x, ts = w.series[0], w.tsamp
     n = x.size
     cfg = oracle.config(n, ts)
     x0 = oracle.mean_subtract(x)
     _say("full size: 2^23, 16 templates")
-    with tb.Plan(batch_templates=8) as plan:
+    with tb.Plan() as plan:
         sid = plan.load_series(x, ts)
         cg = plan.search(sid, w.templates)
         tm0 = tuple(float(v) for v in w.templates[0])
@@ -315,12 +318,10 @@ def test_full_size_circular_survey(tb):
     R.check_power(g["power"], st["p"], st["med"], 4096)
     R.check_medians(g["medians"], st["med"])
     R.check_sums(g["sums"], st["s"])
-    pick = [0, 7, 15]
-    co = oracle.search(x0, cfg, w.templates[pick], series_id=int(sid))
-    co["template_id"] = np.array(pick, dtype=np.uint32)[co["template_id"]]
-    sub = cg[np.isin(cg["template_id"], pick)]
-    matched, exempt = R.check_candidates(sub, co, [oracle.threshold(1 << l, 6.0) for l in range(5)])
+    co = oracle.search(x0, cfg, w.templates, series_id=int(sid))
+    matched, exempt = R.check_candidates(cg, co, [oracle.threshold(1 << l, 6.0) for l in range(5)])
     _say("  tie-exempt %d, candidates matched %d exempt %d" % (ex, matched, exempt))
+    assert matched > 0
 
 
 def test_grouping_of_gpu_candidates(tb):
