@@ -45,7 +45,8 @@ typedef enum {
                                 count is still exact and the first ring_capacity
                                 records found are returned */
     TB_ERR_NOT_READY = -6,   /* tb_poll / non-blocking tb_get_candidates: still running */
-    TB_ERR_UNKNOWN_ID = -7   /* no such series or request */
+    TB_ERR_UNKNOWN_ID = -7,  /* no such series or request */
+    TB_ERR_TOO_LARGE = -8    /* tb_search_templates_noalloc: the work does not fit its fixed scratch */
 } tb_status;
 
 /* tb_config.flags.  TB_DELAY_SERIES: the Roemer delay of every template is
@@ -173,6 +174,32 @@ tb_status tb_unload_series(tb_plan_t plan, int32_t series_id);
  * non-finite values. */
 tb_status tb_search_templates(tb_plan_t plan, int32_t series_id, const tb_template* t,
                               uint32_t count, uint32_t first_template_id, int64_t* request_id);
+
+/* Allocation-free search, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): tb_search_templates followed by a blocking tb_get_candidates,
+ * with the same kernels and results, that calls no hipMalloc, hipFree or
+ * other allocator.  Everything the search needs beyond the resident series
+ * and the plan's tables (the templates, the FFT exchange buffer, powers,
+ * block medians, delay polynomials, the candidate counter and a ring of
+ * capacity records) is carved from one fixed device array of
+ * TB_NOALLOC_SCRATCH_BYTES (128 MiB) per GPU, set up when the first plan on
+ * that GPU is created and held until the process ends (not counted by
+ * tb_memory).  The work runs on the plan's first lane; templates per launch
+ * are reduced (down to one) until the workspace fits.  Returns when the
+ * candidates are in out (host, capacity records; NULL if capacity is 0),
+ * sorted by (series, template, log2_harm, bin), and *n_total holds the
+ * exact count.  TB_ERR_TOO_LARGE if count templates, capacity ring records
+ * and one template's workspace exceed the array (the workspace alone takes
+ * about 96 MiB at 2^24 samples); TB_ERR_OVERFLOW if more than capacity
+ * candidates were found (the first capacity found are returned); otherwise
+ * the errors of tb_search_templates.  Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents: calls that overlap on
+ * one GPU (from different plans or host threads) race. */
+enum { TB_NOALLOC_SCRATCH_BYTES = 128 << 20 };
+tb_status tb_search_templates_noalloc(tb_plan_t plan, int32_t series_id, const tb_template* t, uint32_t count,
+                                      uint32_t first_template_id, tb_candidate* out, uint64_t capacity,
+                                      uint64_t* n_total);
 
 /* TB_OK once the request's device work has finished (its threshold step of
  * Sec. 2.1 and peak detection of App. A included), TB_ERR_NOT_READY before;

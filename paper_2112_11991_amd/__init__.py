@@ -25,6 +25,8 @@ TB_ERR_DEVICE = -4
 TB_ERR_OVERFLOW = -5
 TB_ERR_NOT_READY = -6
 TB_ERR_UNKNOWN_ID = -7
+TB_ERR_TOO_LARGE = -8
+TB_NOALLOC_SCRATCH_BYTES = 128 << 20  # fixed device scratch of tb_search_templates_noalloc, per GPU
 TB_MEM_HOST = 0
 TB_MEM_DEVICE = 1
 TB_SERIES_WHITENING = 2  # OR into the load flags: whiten once from the series' own spectrum
@@ -86,6 +88,7 @@ EXPORTS = [
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
     "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density", "tb_dedisperse", "tb_set_shape",
+    "tb_search_templates_noalloc",
 ]
 
 
@@ -127,6 +130,7 @@ def _load():
     L.tb_load_series.argtypes = [vp, vp, u64, C.c_double, u32, P(i32)]
     L.tb_unload_series.argtypes = [vp, i32]
     L.tb_search_templates.argtypes = [vp, i32, vp, u32, u32, P(i64)]
+    L.tb_search_templates_noalloc.argtypes = [vp, i32, vp, u32, u32, vp, u64, P(u64)]
     L.tb_poll.argtypes = [vp, i64]
     L.tb_get_candidates.argtypes = [vp, i64, vp, u64, P(u64), C.c_int]
     L.tb_release.argtypes = [vp, i64]
@@ -221,6 +225,21 @@ def tb_search_templates(plan: int, series_id: int, templates, first_template_id:
     _check(_L.tb_search_templates(C.c_void_p(plan), int(series_id), _ptr(arr), len(arr), int(first_template_id),
                                   C.byref(rid)), "tb_search_templates")
     return rid.value
+
+
+def tb_search_templates_noalloc(plan: int, series_id: int, templates, first_template_id: int = 0,
+                                capacity: int = 1 << 16, allow_overflow: bool = False):
+    """The allocation-free search (blocking): (sorted candidates, n_total).
+    On overflow (allow_overflow) the capacity records kept are returned."""
+    arr = as_templates(templates)
+    out = np.zeros(int(capacity), dtype=CANDIDATE_DTYPE)
+    n = C.c_uint64(0)
+    st = _L.tb_search_templates_noalloc(C.c_void_p(plan), int(series_id), _ptr(arr), len(arr),
+                                        int(first_template_id), _ptr(out) if out.size else None, out.size,
+                                        C.byref(n))
+    if not (st == TB_ERR_OVERFLOW and allow_overflow):
+        _check(st, "tb_search_templates_noalloc")
+    return out[:min(out.size, int(n.value))], int(n.value)
 
 
 def tb_poll(plan: int, request_id: int) -> bool:
@@ -455,6 +474,11 @@ class Plan:
         finally:
             self.release(rid)
         return cands
+
+    def search_noalloc(self, sid, templates, first_template_id=0, capacity=1 << 16, allow_overflow=False):
+        """The allocation-free search: (sorted candidates, n_total)."""
+        return tb_search_templates_noalloc(self.handle, sid, templates, first_template_id, capacity,
+                                           allow_overflow)
 
     def inspect(self, sid, template, want=("src", "power", "medians", "sums")):
         return tb_inspect_template(self.handle, sid, template, self.series_n[sid], self.cfg.harm_max,

@@ -530,6 +530,33 @@ hipError_t sync_lanes(tb_plan_t p)
     return e;
 }
 
+// A ring record {template, bin, series << 8 | log2 h, S} as a candidate with
+// its significance and fundamental frequency k / (h T).
+void to_candidate(const uint4& q, double T, tb_candidate& c)
+{
+    std::memset(&c, 0, sizeof(c));
+    c.template_id = q.x;
+    c.bin = q.y;
+    c.series_id = q.z >> 8;
+    c.log2_harm = (uint8_t)(q.z & 0xff);
+    float pw;
+    std::memcpy(&pw, &q.w, sizeof(pw));
+    c.power = pw;
+    const int h = 1 << c.log2_harm;
+    c.sigma = (float)fold_sigma(h, (double)pw);
+    c.freq_hz = (double)c.bin / ((double)h * T);
+}
+
+void sort_candidates(tb_candidate* c, size_t n)
+{
+    std::sort(c, c + n, [](const tb_candidate& a, const tb_candidate& b) {
+        if (a.series_id != b.series_id) return a.series_id < b.series_id;
+        if (a.template_id != b.template_id) return a.template_id < b.template_id;
+        if (a.log2_harm != b.log2_harm) return a.log2_harm < b.log2_harm;
+        return a.bin < b.bin;
+    });
+}
+
 tb_status fetch(tb_plan_t p, Req& r)
 {
     if (r.fetched) return TB_OK;
@@ -544,32 +571,84 @@ tb_status fetch(tb_plan_t p, Req& r)
                               p->copy_stream));
         TB_TRY(hipStreamSynchronize(p->copy_stream));
     }
-    double T = (double)r.n * r.tsamp;
+    const double T = (double)r.n * r.tsamp;
     r.cands.resize((size_t)keep);
-    for (size_t i = 0; i < keep; ++i) {
-        const uint4& q = raw[i];
-        tb_candidate& c = r.cands[i];
-        std::memset(&c, 0, sizeof(c));
-        c.template_id = q.x;
-        c.bin = q.y;
-        c.series_id = q.z >> 8;
-        c.log2_harm = (uint8_t)(q.z & 0xff);
-        float pw;
-        std::memcpy(&pw, &q.w, sizeof(pw));
-        c.power = pw;
-        int h = 1 << c.log2_harm;
-        c.sigma = (float)fold_sigma(h, (double)pw);
-        c.freq_hz = (double)c.bin / ((double)h * T);
-    }
-    std::sort(r.cands.begin(), r.cands.end(), [](const tb_candidate& a, const tb_candidate& b) {
-        if (a.series_id != b.series_id) return a.series_id < b.series_id;
-        if (a.template_id != b.template_id) return a.template_id < b.template_id;
-        if (a.log2_harm != b.log2_harm) return a.log2_harm < b.log2_harm;
-        return a.bin < b.bin;
-    });
+    for (size_t i = 0; i < keep; ++i) to_candidate(raw[i], T, r.cands[i]);
+    sort_candidates(r.cands.data(), r.cands.size());
     r.total = total;
     r.fetched = true;
     return TB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Fixed scratch of the allocation-free search (tb_search_templates_noalloc).
+// The library's code object is loaded on every GPU it runs on, so each GPU
+// holds its own copy of this array, at its own address, until the process
+// ends.  In host code the name is only a stand-in: the device address on a
+// GPU comes from hipGetSymbolAddress with that GPU current (done once per
+// device, when its first plan is created) and is the only thing host code
+// hands to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[TB_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Device address of the scratch on device dev, which must be current.
+hipError_t scratch_setup(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[dev]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch[dev] = (char*)ptr;
+    return hipSuccess;
+}
+
+char* scratch_of(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[dev];
+}
+
+// Request part (templates, prepared templates, counter, ring), then a
+// workspace for B templates per wave laid out as get_slots lays out its own;
+// B is the plan's wave size, halved until everything fits the scratch.
+struct ScratchLayout {
+    ReqLayout req;
+    Slots ws;
+    size_t off_y = 0, off_p = 0, off_m = 0, off_q = 0, off_k = 0, total = 0;
+};
+
+bool scratch_layout(const tb_plan_t p, const Geometry& g, uint32_t count, uint64_t cap, ScratchLayout* out)
+{
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    ScratchLayout L;
+    L.req = req_layout(count, cap);
+    for (int B = default_batch(p, g.M);; B = std::max(1, B / 2)) {
+        Slots& s = L.ws;
+        s.B = B;
+        s.BY = (int)std::max<int64_t>(1, std::min<int64_t>(B, ((int64_t)1 << 24) / g.M));
+        s.y_stride = (size_t)g.M;
+        s.p_stride = ((size_t)g.M + 1 + 63) & ~(size_t)63;
+        s.med_stride = ((size_t)g.nblk + 63) & ~(size_t)63;
+        s.poly_stride = (size_t)std::min<int64_t>(g.TE, g.M) / 8;
+        L.off_y = al(L.req.total);
+        L.off_p = L.off_y + al(sizeof(float2) * s.y_stride * s.BY);
+        L.off_m = L.off_p + al(sizeof(float) * s.p_stride * s.B);
+        L.off_q = L.off_m + al(sizeof(float) * s.med_stride * s.B);
+        L.off_k = L.off_q + al(sizeof(ChunkPoly) * s.poly_stride * s.B);
+        L.total = L.off_k + al(sizeof(int32_t) * (size_t)s.B);
+        if (L.total <= (size_t)TB_NOALLOC_SCRATCH_BYTES) {
+            *out = L;
+            return true;
+        }
+        if (B == 1) return false;
+    }
 }
 
 }  // namespace
@@ -607,6 +686,7 @@ const char* tb_strerror(tb_status s)
     case TB_ERR_OVERFLOW: return "candidate ring overflowed";
     case TB_ERR_NOT_READY: return "not ready";
     case TB_ERR_UNKNOWN_ID: return "unknown id";
+    case TB_ERR_TOO_LARGE: return "does not fit the fixed scratch of the allocation-free search";
     }
     return "unknown status";
 }
@@ -630,6 +710,8 @@ tb_status tb_plan(const tb_config* cfg, tb_plan_t* out)
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || c.device < 0 || c.device >= ndev) return TB_ERR_DEVICE;
     if (hipSetDevice(c.device) != hipSuccess) return TB_ERR_DEVICE;
+    // the allocation-free search's scratch on this device
+    if (scratch_setup(c.device) != hipSuccess) return TB_ERR_DEVICE;
     tb_plan_t p = new (std::nothrow) tb_plan_s();
     if (!p) return TB_ERR_OOM;
     p->cfg = c;
@@ -1082,6 +1164,76 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
     p->reqs.emplace(rid, std::move(r));
     *request_id = rid;
     return TB_OK;
+}
+
+tb_status tb_search_templates_noalloc(tb_plan_t p, int32_t sid, const tb_template* t, uint32_t count,
+                                      uint32_t first, tb_candidate* out, uint64_t capacity, uint64_t* n_total)
+{
+    if (!p || !n_total || (count && !t) || (capacity && !out) || capacity > 0xffffffffull)
+        return TB_ERR_INVALID_ARG;
+    for (uint32_t i = 0; i < count; ++i)
+        if (!valid_template(t[i])) return TB_ERR_INVALID_ARG;
+    if ((uint64_t)first + count > 0xffffffffull) return TB_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(p->mu);
+    auto sit = p->series.find(sid);
+    if (sit == p->series.end()) return TB_ERR_UNKNOWN_ID;
+    TB_TRY(hipSetDevice(p->cfg.device));
+    const SeriesRec& sr = sit->second;
+    for (uint32_t i = 0; i < count; ++i)
+        if (!delay_fits(p, t[i], sr.tsamp)) return TB_ERR_INVALID_ARG;
+    // the series' length was laid out (tables, tile order) when it was loaded
+    auto git = p->geo.find(ilog2((uint64_t)sr.n));
+    char* base = scratch_of(p->cfg.device);
+    if (git == p->geo.end() || !base) return TB_ERR_DEVICE;
+    const Geometry& g = git->second.g;
+    ScratchLayout L;
+    if (!scratch_layout(p, g, count, capacity, &L)) return TB_ERR_TOO_LARGE;
+    Slots ws = L.ws;
+    ws.Y = (float2*)(base + L.off_y);
+    ws.P = (float*)(base + L.off_p);
+    ws.med = (float*)(base + L.off_m);
+    ws.poly = (ChunkPoly*)(base + L.off_q);
+    ws.pok = (int32_t*)(base + L.off_k);
+    tb_template* d_t = (tb_template*)(base + L.req.off_t);
+    TmplDev* d_tm = (TmplDev*)(base + L.req.off_tm);
+    uint32_t* counter = (uint32_t*)(base + L.req.off_cnt);
+    uint4* ring = (uint4*)(base + L.req.off_ring);
+    hipStream_t s = p->stream;
+    const PeakParams pp = peak_params(p, sr.n, sr.tsamp, (uint32_t)sid, first, capacity);
+    // the counter starts at zero (a fill kernel, not a memset)
+    hipError_t e = launch_fill_u32(counter, 0u, 1, s);
+    if (e == hipSuccess && count)
+        e = hipMemcpyAsync(d_t, t, sizeof(tb_template) * count, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_template_prep(d_t, count, d_tm, delay_model(p), s);
+    const Inspect none;
+    for (uint32_t w0 = 0; w0 < count && e == hipSuccess;) {
+        const int nslots = (int)std::min<uint32_t>((uint32_t)ws.B, count - w0);
+        e = launch_wave(g, sr.d, sr.tsamp, d_tm, (int)w0, nslots, ws, sr.fac, sr.zap, sr.nzap, pp, ring, counter,
+                        none, s, nullptr);
+        w0 += (uint32_t)nslots;
+    }
+    uint32_t total = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const uint64_t keep = std::min<uint64_t>(total, capacity);
+    if (e == hipSuccess && keep) e = hipMemcpyAsync(out, ring, keep * sizeof(uint4), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return TB_ERR_DEVICE;
+    // The 16-byte ring records now fill the front of out; widen them in place
+    // from the last one down.  Candidate i covers the bytes of records 2i and
+    // 2i + 1, which are read (i = 0) or already widened (i > 0) by then.
+    static_assert(sizeof(tb_candidate) == 2 * sizeof(uint4), "candidate record sizes");
+    const double T = (double)sr.n * sr.tsamp;
+    for (uint64_t i = keep; i-- > 0;) {
+        uint4 q;
+        std::memcpy(&q, (const char*)out + i * sizeof(uint4), sizeof(q));
+        tb_candidate c;
+        to_candidate(q, T, c);
+        std::memcpy(&out[i], &c, sizeof(c));
+    }
+    sort_candidates(out, (size_t)keep);
+    *n_total = total;
+    return total > capacity ? TB_ERR_OVERFLOW : TB_OK;
 }
 
 tb_status tb_poll(tb_plan_t p, int64_t rid)
