@@ -28,6 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 instruction
+# takes four cycles of a 16-lane SIMD; packed FP32 is not used)
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNELS = ["k_chunk_polys (per-template delay polynomials)", "k_fft1 (resample + FFT pass 1)",
            "k_fft2 (FFT pass 2 + R2C + power)", "k_median (whitening medians)", "k_whiten (whitening)",
            "k_harmsum (harmonic sum + peaks)"]
@@ -85,10 +88,25 @@ def kernel_bytes(n: int, templates_per_launch: float, tile: int = 8192, series_w
             6.0 * n * b + (2.0 * n if series_whitening else 0.0), 2.0 * n * b, 4.0 * n * b, 2.0 * n * b]
 
 
-def traffic_record(kernel: str, workload_name: str):
-    """Measured HBM traffic per launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload_name))
+def wave_shape(n: int, batch: int = 0):
+    """Templates per wave B and per pass-1/2 launch BY the library uses for
+    series of n samples (mirrors its defaults)."""
+    M = n // 2
+    B = batch or min(256, max(4, (1 << 26) // M))
+    return B, max(1, min(B, (1 << 24) // M))
+
+
+def pass1_launches(n: int, templates: int, batch: int = 0) -> int:
+    """Pass-1 launches (each reads the series once) of one request."""
+    B, BY = wave_shape(n, batch)
+    full, rest = divmod(templates, B)
+    return full * (-(-B // BY)) + (-(-rest // BY) if rest else 0)
+
+
+def traffic_record(kernel: str, workload_name: str, what: str = "traffic"):
+    """A committed rocprofv3 counter record (HBM traffic, or VALU
+    instructions) per launch, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_%s.json" % (what, kernel, workload_name))
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -101,11 +119,22 @@ def traffic_record(kernel: str, workload_name: str):
     return rec
 
 
+def host_threads():
+    """Threads for the CPU oracle: every core this process may use, i.e. its
+    CPU affinity, capped by OMP_NUM_THREADS where the host sets it (a GPU
+    job's share of a shared host); with the basis stated."""
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    omp = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    if omp and omp < aff:
+        return omp, "OMP_NUM_THREADS=%d (CPU affinity %d, nproc %s)" % (omp, aff, os.cpu_count())
+    return aff, "CPU affinity %d (nproc %s)" % (aff, os.cpu_count())
+
+
 def cpu_baseline(w, seconds_hint: float, series_whitening: bool = False, delay_series: bool = False):
     import oracle
 
     oracle.build()
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    threads, share = host_threads()
     x = w.series[0]
     n = x.size
     cfg = oracle.config(n, w.tsamp, series_whitening=series_whitening, delay_model=int(delay_series))
@@ -121,7 +150,7 @@ def cpu_baseline(w, seconds_hint: float, series_whitening: bool = False, delay_s
     return {"value": count / dt, "unit": "templates/s", "cores": threads, "kind": "oracle",
             "sample": "first %d templates of the same bank on the same series (N=%d), FP64 C oracle, %d threads, "
                       "%.1f s" % (count, n, threads, dt),
-            "single_thread_templates_per_s": 1.0 / one}
+            "single_thread_templates_per_s": 1.0 / one, "cores_basis": share, "nproc": os.cpu_count()}
 
 
 def kernel_report(plan, n_avg: float, workload_name: str, tile: int, series_whitening: bool = False):
@@ -138,9 +167,21 @@ def kernel_report(plan, n_avg: float, workload_name: str, tile: int, series_whit
     dom = max(range(len(KERNELS)), key=lambda k: ms[k])
     d = per[dom]
     tr = traffic_record(d["kernel"], workload_name)
-    roof = {"bound": "hbm", "kernel": d["kernel"], "achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": d["gbs"] / PEAK_HBM_GBS, "traffic": None if tr is None else tr["bytes_per_launch"],
-            "avg_launch_ms": d["avg_ms"], "templates_per_launch": tmpl / max(1, int(launches[dom]))}
+    hbm = {"achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": d["gbs"] / PEAK_HBM_GBS}
+    roof = dict(bound="hbm", kernel=d["kernel"], **hbm)
+    roof.update({"traffic": None if tr is None else tr["bytes_per_launch"], "avg_launch_ms": d["avg_ms"],
+                 "templates_per_launch": tmpl / max(1, int(launches[dom]))})
+    vr = traffic_record(d["kernel"], workload_name, "valu")
+    if vr is not None:
+        # VALU issue: the counted wave instructions x 64 lanes over the live launch time
+        lanes = 64.0 * vr["valu_insts_per_dispatch"]
+        ach = lanes / (d["avg_ms"] * 1e-3)
+        valu = {"achieved": ach / 1e12, "peak": PEAK_VALU_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                "frac": ach / PEAK_VALU_LANE_OPS, "lane_ops_per_point": vr.get("lane_ops_per_point")}
+        roof["hbm"], roof["valu"] = hbm, valu
+        if valu["frac"] > hbm["frac"]:
+            roof.update(bound="alu", achieved=valu["achieved"], peak=valu["peak"], unit=valu["unit"],
+                        frac=valu["frac"])
     return per, roof
 
 
@@ -354,6 +395,18 @@ def run_bank(args, tb, torch):
            "config": conf, "candidates_per_step": ncand // max(1, args.steps),
            "algorithmic_gbs": 12.0 * samples_total * ntemp * args.steps / dt / 1e9}
     out["algorithmic_hbm_frac"] = out["algorithmic_gbs"] / PEAK_HBM_GBS
+    # whole path: 12n bytes per template plus the series read of every pass-1 launch
+    batch = args.batch or 0
+    if args.autotune:
+        batch = None
+    if batch is not None:
+        launches = sum(pass1_launches(int(x.size), len(c), batch) for x in w.series for c in chunks if len(c))
+        step_bytes = 12.0 * samples_total * ntemp + sum(
+            4.0 * x.size * pass1_launches(int(x.size), len(c), batch) for x in w.series for c in chunks if len(c))
+        gbs = step_bytes / (ms_step * 1e-3) / 1e9
+        out["path_roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                "frac": gbs / PEAK_HBM_GBS, "bytes_per_step": step_bytes,
+                                "pass1_launches_per_step": launches}
     if not args.no_profile:
         out["kernels"], out["roofline"] = kernel_report(plan, samples_total / len(w.series), profile_name,
                                                      conf["tile_points"], args.series_whitening)
@@ -364,6 +417,18 @@ def run_bank(args, tb, torch):
     if args.workload == "c2":
         out["bank"] = bank_report(tb, not args.no_cpu_baseline)
         out["dedispersion"] = dedispersion_report(tb, torch, not args.no_cpu_baseline)
+        if not args.no_batching:
+            log("batched vs one template per launch ...")
+            out["batching"] = batching_report(tb)
+            out["batched_vs_plain"] = {k: v["batched_vs_plain"] for k, v in out["batching"]["per_length"].items()}
+        if args.serve_requests:
+            out["serving"] = served(tb, torch, args.serve_requests, 4, False)
+            half = out["serving"]["half_capacity"]
+            # latency of the stream at half its measured capacity (at the trace's own
+            # rate the latency is queueing and grows with the trace)
+            out["p50_ms"], out["p99_ms"] = half["p50_ms"], half["p99_ms"]
+            out["latency_basis"] = "%d-request served trace at %.2f req/s (half the measured capacity)" % (
+                args.serve_requests, half["rate_req_s"])
     if args.workload == "c4" and not args.no_plain:
         idx = list(range(min(4, len(w.series))))
         rates = plain_vs_batched(tb, w, idx, 256)
@@ -377,16 +442,20 @@ def run_bank(args, tb, torch):
     return out
 
 
-def run_served(args, tb, torch):
-    """c5: Poisson request stream served by the continuous-batching loop."""
+def served(tb, torch, nreq, lanes=4, with_plain=True):
+    """The continuous-batching loop over a Poisson request trace (50/s; pool of
+    16 series of 2^20..2^24 samples; 256-4096 templates per request, 30%%
+    elliptical; 200 GB HBM budget): throughput and p50/p99 latency (arrival ->
+    candidates retrievable) with the trace at its own rate (saturating: the
+    trace offers several times the capacity, so latency is queueing) and
+    stretched to half the measured capacity (the latency floor)."""
     import synth
     from paper_2112_11991_amd.serve import Request, serve
 
-    nreq = args.requests
     lens, reqs = synth.request_trace(nreq)
     series = synth.pool_series(lens)
     tsamp = 64e-6
-    plan = tb.Plan(lanes=args.lanes or 4, ring_capacity=1 << 16, hbm_budget_bytes=200 * 10**9, fmin_hz=1.0)
+    plan = tb.Plan(lanes=lanes, ring_capacity=1 << 16, hbm_budget_bytes=200 * 10**9, fmin_hz=1.0)
     sids = [plan.load_series(s, tsamp) for s in series]
     for n in sorted(set(lens)):
         plan.search(sids[lens.index(n)], reqs[0]["templates"][:8])
@@ -398,23 +467,19 @@ def run_served(args, tb, torch):
     log("serving %d requests at 50/s ..." % nreq)
     rep = serve(plan, sids, lens, requests(), realtime=True)
     log("  p50 %.1f ms p99 %.1f ms, %.0f templates/s" % (rep.p50_ms, rep.p99_ms, rep.templates_per_s))
-    # the same requests at half the measured capacity: the latency floor
     scale = 50.0 / (0.5 * rep.n_requests / rep.makespan_s)
     log("serving at %.2f req/s ..." % (50.0 / scale))
     rep2 = serve(plan, sids, lens, requests(), realtime=True, time_scale=scale)
     log("  p50 %.1f ms p99 %.1f ms" % (rep2.p50_ms, rep2.p99_ms))
     plan.close()
-    out = {"metric": "served templates/s and p50/p99 latency (request stream)", "value": rep.templates_per_s,
-           "unit": "templates/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": rep.makespan_s * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "served stream: %d requests, Poisson 50/s, pool of 16 series 2^20..2^24 at 64 us, "
-                                  "256-4096 templates each, 30%% elliptical" % nreq},
-           "p50_ms": rep.p50_ms, "p99_ms": rep.p99_ms,
-           "saturation": rep.as_dict(), "half_capacity": dict(rep2.as_dict(), rate_req_s=50.0 / scale)}
-    if not args.no_plain:
+    out = {"workload": "served stream: %d requests, Poisson 50/s, pool of 16 series 2^20..2^24 at 64 us, 256-4096 "
+                       "templates each, 30%% elliptical, HBM budget 200 GB" % nreq,
+           "requests": nreq, "templates_per_s": rep.templates_per_s, "saturation": rep.as_dict(),
+           "half_capacity": dict(rep2.as_dict(), rate_req_s=50.0 / scale)}
+    if with_plain:
         rates = {}
         sub = requests()[:6]
-        for name, kw in (("plain", dict(batch_templates=1, lanes=1)), ("served", dict(lanes=args.lanes or 4))):
+        for name, kw in (("plain", dict(batch_templates=1, lanes=1)), ("served", dict(lanes=lanes))):
             with tb.Plan(ring_capacity=1 << 16, **kw) as pp:
                 ps = {r.series: None for r in sub}
                 for k in ps:
@@ -433,6 +498,47 @@ def run_served(args, tb, torch):
     return out
 
 
+def batching_report(tb, lengths=(20, 21, 22, 23), ntemp=256, tsamp=64e-6, reps=2):
+    """Batched search (the library's waves of 16-128 templates, four lanes)
+    against the one-template-per-launch path (every kernel launched for a
+    single template, one stream) on the same noise series and the same 256
+    circular templates, for each series length of the uneven-length search."""
+    import synth
+
+    rng = np.random.default_rng(2112)
+    bank = synth.uniform_templates(rng, ntemp, (1.0, 10.0), (0.0, 2.0))
+    out = {"templates": ntemp, "unit": "templates/s", "per_length": {}}
+    for lg in lengths:
+        x = rng.standard_normal(1 << lg).astype(np.float32)
+        rates = {}
+        for name, kw in (("plain", dict(batch_templates=1, lanes=1)), ("batched", dict(lanes=4))):
+            with tb.Plan(ring_capacity=1 << 16, **kw) as plan:
+                sid = plan.load_series(x, tsamp)
+                plan.search(sid, bank[:8])
+                best = 0.0
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    plan.search(sid, bank)
+                    best = max(best, ntemp / (time.perf_counter() - t0))
+                rates[name] = best
+        out["per_length"]["2^%d" % lg] = {"plain": rates["plain"], "batched": rates["batched"],
+                                          "batched_vs_plain": rates["batched"] / rates["plain"]}
+        log("  2^%d: plain %.0f, batched %.0f templates/s" % (lg, rates["plain"], rates["batched"]))
+    return out
+
+
+def run_served(args, tb, torch):
+    """c5: Poisson request stream served by the continuous-batching loop."""
+    rep = served(tb, torch, args.requests, args.lanes or 4, not args.no_plain)
+    sat = rep["saturation"]
+    out = {"metric": "served templates/s and p50/p99 latency (request stream)", "value": rep["templates_per_s"],
+           "unit": "templates/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": sat["makespan_s"] * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": rep.pop("workload")}, "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"]}
+    out.update(rep)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -440,7 +546,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--templates", type=int, default=None)
-    ap.add_argument("--requests", type=int, default=100)
+    ap.add_argument("--requests", type=int, default=400, help="requests of the c5 trace")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the short served trace in the default run (0 = none)")
+    ap.add_argument("--no-batching", action="store_true",
+                    help="skip the per-length batched vs one-template-per-launch comparison of the default run")
     ap.add_argument("--batch", type=int, default=0, help="templates in flight per launch (0 = library default)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--split", type=int, default=1, help="requests the bank is cut into per series (spread over lanes)")
