@@ -32,9 +32,9 @@ PEAK_HBM_GBS = 8000.0
 # takes four cycles of a 16-lane SIMD; packed FP32 is not used)
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 KERNELS = ["k_chunk_polys (per-template delay polynomials)", "k_fft1 (resample + FFT pass 1)",
-           "k_fft2 (FFT pass 2 + R2C + power)", "k_median (whitening medians)", "k_whiten (whitening)",
+           "k_fft2 (FFT pass 2 + R2C + power)", "k_median_whiten (block medians + whitening)", "(unused class)",
            "k_harmsum (harmonic sum + peaks)"]
-KERNEL_SHORT = ["k_chunk_polys", "k_fft1", "k_fft2", "k_median", "k_whiten", "k_harmsum"]
+KERNEL_SHORT = ["k_chunk_polys", "k_fft1", "k_fft2", "k_median_whiten", "-", "k_harmsum"]
 PROFILE_EVERY = 16  # time one wave in this many inside the timed region
 METRIC = "templates/s (resample+FFT+harmsum+peaks) at N=2^23 FP32"
 
@@ -80,12 +80,12 @@ def kernel_bytes(n: int, templates_per_launch: float, tile: int = 8192, series_w
     the delay polynomials write 48 B per 16 tile points; pass 1 writes the
     4n-byte exchange per template and reads the 4n-byte series once per launch;
     pass 2 reads 4n and writes 2n (and, for a series whitened once, reads its
-    2n-byte factors once per launch); the medians read the 2n-byte spectrum,
-    the whitening reads and rewrites it, the harmonic sum reads it once (first
-    touch)."""
+    2n-byte factors once per launch); the medians and whitening read the
+    2n-byte spectrum and write the whitened one; the harmonic sum reads it once
+    (first touch)."""
     b = templates_per_launch
     return [48.0 * min(tile, n // 2) / 16 * b, 4.0 * n * b + 4.0 * n,
-            6.0 * n * b + (2.0 * n if series_whitening else 0.0), 2.0 * n * b, 4.0 * n * b, 2.0 * n * b]
+            6.0 * n * b + (2.0 * n if series_whitening else 0.0), 4.0 * n * b, 0.0, 2.0 * n * b]
 
 
 def wave_shape(n: int, batch: int = 0):
@@ -158,19 +158,20 @@ def kernel_report(plan, n_avg: float, workload_name: str, tile: int, series_whit
     plan.profile(False)
     per = []
     for k in range(len(KERNELS)):
+        if not launches[k]:
+            continue
         L = max(1, int(launches[k]))
         avg_ms = ms[k] / L
         byt = kernel_bytes(int(n_avg), tmpl / L, tile, series_whitening)[k]
         per.append({"kernel": KERNEL_SHORT[k], "desc": KERNELS[k], "launches": int(launches[k]), "avg_ms": avg_ms,
                     "total_ms": float(ms[k]), "bytes_per_launch": byt,
                     "gbs": byt / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else None})
-    dom = max(range(len(KERNELS)), key=lambda k: ms[k])
-    d = per[dom]
+    d = max(per, key=lambda r: r["total_ms"])
     tr = traffic_record(d["kernel"], workload_name)
     hbm = {"achieved": d["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": d["gbs"] / PEAK_HBM_GBS}
     roof = dict(bound="hbm", kernel=d["kernel"], **hbm)
     roof.update({"traffic": None if tr is None else tr["bytes_per_launch"], "avg_launch_ms": d["avg_ms"],
-                 "templates_per_launch": tmpl / max(1, int(launches[dom]))})
+                 "templates_per_launch": tmpl / max(1, d["launches"])})
     vr = traffic_record(d["kernel"], workload_name, "valu")
     if vr is not None:
         # VALU issue: the counted wave instructions x 64 lanes over the live launch time

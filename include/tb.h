@@ -219,16 +219,19 @@ tb_status tb_poll(tb_plan_t plan, int64_t request_id);
 tb_status tb_get_candidates(tb_plan_t plan, int64_t request_id, tb_candidate* out,
                             uint64_t capacity, uint64_t* n_total, int blocking);
 
-/* Waits for and forgets a request, freeing its device memory.  Resource
- * management only: the paper defines no such step.  TB_ERR_UNKNOWN_ID for an
- * unknown request. */
+/* Waits for and forgets a request.  Its device buffer and pinned template
+ * copy go back to the plan, which keeps up to 32 of each for later requests
+ * (so that steady-state submits allocate nothing) and frees them in
+ * tb_destroy.  Resource management only: the paper defines no such step.
+ * TB_ERR_UNKNOWN_ID for an unknown request. */
 tb_status tb_release(tb_plan_t plan, int64_t request_id);
 
 /* Blocks until every queued request of the plan has finished. */
 tb_status tb_synchronize(tb_plan_t plan);
 
-/* Device memory the plan holds (series, workspaces, tables, queued requests)
- * and its current HBM budget (0 = none).  Either pointer may be NULL. */
+/* Device memory the plan holds (series, workspaces, tables, requests not yet
+ * released; the idle request buffers it keeps for reuse are not counted) and
+ * its current HBM budget (0 = none).  Either pointer may be NULL. */
 tb_status tb_memory(tb_plan_t plan, uint64_t* held_bytes, uint64_t* budget_bytes);
 
 /* Changes the admission budget; 0 removes it.  Memory already held is kept;
@@ -267,7 +270,8 @@ tb_status tb_profile(tb_plan_t plan, int every);
 /* Waits for queued work and reports, per kernel class, the summed device
  * milliseconds and launch counts of the timed waves since profiling started:
  *   [0] delay polynomials, [1] resample + FFT pass 1, [2] FFT pass 2 + power,
- *   [3] block medians, [4] whitening, [5] harmonic sum + threshold + compaction.
+ *   [3] block medians and whitening (one kernel), [4] no longer used (0),
+ *   [5] harmonic sum + threshold + compaction.
  * *templates receives the number of templates the timed waves processed.
  * Any output pointer may be NULL. */
 tb_status tb_profile_read(tb_plan_t plan, double ms[6], uint64_t launches[6], uint64_t* templates);

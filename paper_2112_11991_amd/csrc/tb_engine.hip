@@ -131,6 +131,7 @@ void free_slots(Slots& s)
 {
     hipFree(s.Y);
     hipFree(s.P);
+    hipFree(s.Q);
     hipFree(s.med);
     hipFree(s.poly);
     hipFree(s.pok);
@@ -156,7 +157,9 @@ struct Req {
     int64_t n = 0;
     double tsamp = 0;
     char* dmem = nullptr;       // templates (device copy), prepared templates, counter, ring
+    size_t dmem_size = 0;
     tb_template* h_t = nullptr; // pinned host copy
+    size_t h_t_size = 0;
     size_t bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     bool fetched = false;
@@ -181,6 +184,10 @@ struct tb_plan_s {
     uint64_t held = 0;
     double thr[5] = {0, 0, 0, 0, 0};
     double* d_partial = nullptr;
+    // Request buffers kept for reuse after tb_release (device slabs and pinned
+    // template copies, by size): steady-state submits allocate nothing.
+    std::multimap<size_t, char*> dev_pool;
+    std::multimap<size_t, tb_template*> pin_pool;
     uint32_t prof_every = 0;                           // time every k-th wave; 0 = off
     uint64_t prof_wave = 0;                            // waves queued since profiling started
     std::vector<Marks> prof_events;                    // marks of every timed wave
@@ -378,10 +385,10 @@ tb_status get_slots(tb_plan_t p, int lane, const Geometry& g, Slots** out)
     size_t by = sizeof(float2) * s.y_stride * s.BY, bp = sizeof(float) * s.p_stride * s.B,
            bm = sizeof(float) * s.med_stride * s.B, bq = sizeof(ChunkPoly) * s.poly_stride * s.B,
            bk = sizeof(int32_t) * (size_t)s.B;
-    rec.bytes = by + bp + bm + bq + bk;
+    rec.bytes = by + 2 * bp + bm + bq + bk;
     tb_status st = reserve(p, rec.bytes);
     if (st) return st;
-    if (hipMalloc(&s.Y, by) != hipSuccess || hipMalloc(&s.P, bp) != hipSuccess ||
+    if (hipMalloc(&s.Y, by) != hipSuccess || hipMalloc(&s.P, bp) != hipSuccess || hipMalloc(&s.Q, bp) != hipSuccess ||
         hipMalloc(&s.med, bm) != hipSuccess || hipMalloc(&s.poly, bq) != hipSuccess ||
         hipMalloc(&s.pok, bk) != hipSuccess) {
         free_slots(s);
@@ -439,14 +446,69 @@ bool valid_template(const tb_template& t)
            t.ecc >= 0.0 && t.ecc < 1.0;
 }
 
+// Request buffers: a pooled one of at least `need` bytes and at most twice
+// that, else a new one of `need` rounded up to 1 MiB (device) or 4 KiB
+// (pinned host).  Returned buffers are kept, up to kPoolKeep of each kind;
+// the plan frees them in tb_destroy.  Only buffers of requests whose device
+// work has completed are returned.
+constexpr size_t kPoolKeep = 32;
+
+template <class T>
+T* pool_take(std::multimap<size_t, T*>& pool, size_t need, size_t* got)
+{
+    auto it = pool.lower_bound(need);
+    if (it == pool.end() || it->first > 2 * need) return nullptr;
+    T* ptr = it->second;
+    *got = it->first;
+    pool.erase(it);
+    return ptr;
+}
+
+template <class T, class F>
+void pool_give(std::multimap<size_t, T*>& pool, size_t bytes, T* ptr, F release)
+{
+    if (!ptr) return;
+    pool.emplace(bytes, ptr);
+    if (pool.size() > kPoolKeep) {
+        auto it = pool.begin();  // the smallest goes
+        release(it->second);
+        pool.erase(it);
+    }
+}
+
+char* take_device(tb_plan_t p, size_t need, size_t* got)
+{
+    if (char* d = pool_take(p->dev_pool, need, got)) return d;
+    const size_t size = (need + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+    char* d = nullptr;
+    if (hipMalloc((void**)&d, size) != hipSuccess) {
+        // memory may sit in the pool: give it back and try once more
+        for (auto& kv : p->dev_pool) hipFree(kv.second);
+        p->dev_pool.clear();
+        if (hipMalloc((void**)&d, size) != hipSuccess) return nullptr;
+    }
+    *got = size;
+    return d;
+}
+
+tb_template* take_pinned(tb_plan_t p, size_t need, size_t* got)
+{
+    if (tb_template* h = pool_take(p->pin_pool, need, got)) return h;
+    const size_t size = (need + 4095) & ~(size_t)4095;
+    void* h = nullptr;
+    if (hipHostMalloc(&h, size, hipHostMallocDefault) != hipSuccess) return nullptr;
+    *got = size;
+    return (tb_template*)h;
+}
+
 void free_request(tb_plan_t p, Req& r)
 {
     if (r.ev0) hipEventDestroy(r.ev0);
     if (r.ev1) hipEventDestroy(r.ev1);
     for (hipEvent_t e : r.joins) hipEventDestroy(e);
     r.joins.clear();
-    if (r.dmem) hipFreeAsync(r.dmem, p->lanes[r.lane].stream);
-    hipHostFree(r.h_t);
+    pool_give(p->dev_pool, r.dmem_size, r.dmem, [](char* d) { hipFree(d); });
+    pool_give(p->pin_pool, r.h_t_size, r.h_t, [](tb_template* h) { hipHostFree(h); });
     r.dmem = nullptr;
     r.h_t = nullptr;
 }
@@ -621,7 +683,7 @@ char* scratch_of(int dev)
 struct ScratchLayout {
     ReqLayout req;
     Slots ws;
-    size_t off_y = 0, off_p = 0, off_m = 0, off_q = 0, off_k = 0, total = 0;
+    size_t off_y = 0, off_p = 0, off_w = 0, off_m = 0, off_q = 0, off_k = 0, total = 0;
 };
 
 bool scratch_layout(const tb_plan_t p, const Geometry& g, uint32_t count, uint64_t cap, ScratchLayout* out)
@@ -639,7 +701,8 @@ bool scratch_layout(const tb_plan_t p, const Geometry& g, uint32_t count, uint64
         s.poly_stride = (size_t)std::min<int64_t>(g.TE, g.M) / 8;
         L.off_y = al(L.req.total);
         L.off_p = L.off_y + al(sizeof(float2) * s.y_stride * s.BY);
-        L.off_m = L.off_p + al(sizeof(float) * s.p_stride * s.B);
+        L.off_w = L.off_p + al(sizeof(float) * s.p_stride * s.B);
+        L.off_m = L.off_w + al(sizeof(float) * s.p_stride * s.B);
         L.off_q = L.off_m + al(sizeof(float) * s.med_stride * s.B);
         L.off_k = L.off_q + al(sizeof(ChunkPoly) * s.poly_stride * s.B);
         L.total = L.off_k + al(sizeof(int32_t) * (size_t)s.B);
@@ -727,12 +790,6 @@ tb_status tb_plan(const tb_config* cfg, tb_plan_t* out)
         }
     }
     if (ok) p->stream = p->lanes[0].stream;
-    // keep freed request memory in the stream-ordered pool instead of returning it
-    hipMemPool_t pool = nullptr;
-    if (ok && hipDeviceGetDefaultMemPool(&pool, c.device) == hipSuccess && pool) {
-        uint64_t keep = ~0ull;
-        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
     if (!ok || hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc(&p->d_partial, sizeof(double) * 1040) != hipSuccess) {
         for (auto& L : p->lanes)
@@ -755,6 +812,8 @@ tb_status tb_destroy(tb_plan_t p)
         sync_lanes(p);
         for (auto& kv : p->reqs) free_request(p, kv.second);
         sync_lanes(p);
+        for (auto& kv : p->dev_pool) hipFree(kv.second);
+        for (auto& kv : p->pin_pool) hipHostFree(kv.second);
         for (auto& kv : p->series) {
             hipFree(kv.second.d);
             hipFree(kv.second.zap);
@@ -1081,12 +1140,11 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
     ReqLayout L = req_layout(count, r.cap);
     r.bytes = L.total;
     if ((st = reserve(p, r.bytes))) return st;
-    if (hipMallocAsync((void**)&r.dmem, L.total, stream) != hipSuccess) {
-        r.dmem = nullptr;
+    if (!(r.dmem = take_device(p, L.total, &r.dmem_size))) {
         p->held -= r.bytes;
         return TB_ERR_OOM;
     }
-    if (count && hipHostMalloc(&r.h_t, sizeof(tb_template) * count, hipHostMallocDefault) != hipSuccess) {
+    if (count && !(r.h_t = take_pinned(p, sizeof(tb_template) * count, &r.h_t_size))) {
         free_request(p, r);
         p->held -= r.bytes;
         return TB_ERR_OOM;
@@ -1191,6 +1249,7 @@ tb_status tb_search_templates_noalloc(tb_plan_t p, int32_t sid, const tb_templat
     Slots ws = L.ws;
     ws.Y = (float2*)(base + L.off_y);
     ws.P = (float*)(base + L.off_p);
+    ws.Q = (float*)(base + L.off_w);
     ws.med = (float*)(base + L.off_m);
     ws.poly = (ChunkPoly*)(base + L.off_q);
     ws.pok = (int32_t*)(base + L.off_k);

@@ -111,6 +111,7 @@ struct Slots {
     float2* Y = nullptr;   // exchange buffer, BY x M complex
     size_t y_stride = 0;   // complex per slot
     float* P = nullptr;    // power, B x (M + 1), padded
+    float* Q = nullptr;    // whitened power (per-template whitening), same layout as P
     size_t p_stride = 0;
     float* med = nullptr;  // block medians, B x nblk
     size_t med_stride = 0;

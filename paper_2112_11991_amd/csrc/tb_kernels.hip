@@ -904,40 +904,29 @@ __global__ __launch_bounds__(D2 * R / 16) void k_fft2(const float2* __restrict__
 // thread t owns the NBIN/NT consecutive bins from t NBIN/NT on, sums and
 // clears them, and a block-wide prefix sum over the threads finds the digit
 // holding the rank.
+constexpr int MED_BINS = 2048;  // first-digit histogram (bits 30..20)
+
+// Lower median (rank floor((cnt-1)/2)) of a block's values v (IEEE bits,
+// absent entries 0xffffffff), by the three-digit radix selection above.
+// Every thread of the workgroup calls it and gets the median.  hist must be
+// zero on entry and is zero again on return (every pass clears the bins it
+// sums, and later passes only count into bins the first one cleared).
 template <int VPT>
-__global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size_t p_stride, int64_t M, int W,
-                                               float* __restrict__ med, size_t med_stride)
+__device__ __forceinline__ float block_median(const uint32_t (&v)[VPT], int cnt, uint32_t* hist, uint32_t* wsum,
+                                              uint32_t& s_digit, uint32_t& s_rank)
 {
-    constexpr int NW = NT / 64, NC = 1, NB0 = 2048;
-    __shared__ uint32_t hist[NC][NB0];
-    __shared__ uint32_t wsum[NW];
-    __shared__ uint32_t s_digit, s_rank;
-    const int b = blockIdx.x;
+    constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const float* Ps = P + blockIdx.y * p_stride;
-    const int64_t start = 1 + (int64_t)b * W;
-    const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
-    uint32_t v[VPT];
-#pragma unroll
-    for (int i = 0; i < VPT; ++i) {
-        const int q = (int)threadIdx.x + i * NT;
-        // absent entries get the largest key and never match a prefix of a real one
-        v[i] = q < cnt ? __float_as_uint(Ps[start + q]) : 0xffffffffu;
-    }
-#pragma unroll
-    for (int i = 0; i < NC * NB0 / NT; ++i) (&hist[0][0])[threadIdx.x + i * NT] = 0;
-    __syncthreads();
-    uint32_t* myhist = hist[wave & (NC - 1)];
     uint32_t rank = (uint32_t)(cnt - 1) / 2, prefix = 0, mask = 0x80000000u;
 #pragma unroll
     for (int pass = 0; pass < 3; ++pass) {
         const int shift = pass == 0 ? 20 : pass == 1 ? 10 : 0;
-        const int nbin = pass == 0 ? 2048 : 1024;
+        const int nbin = pass == 0 ? MED_BINS : 1024;
         const uint32_t dmask = (uint32_t)nbin - 1;
         const int per = nbin / NT;  // bins per thread: 8, then 4
 #pragma unroll
         for (int i = 0; i < VPT; ++i)
-            if ((v[i] & mask) == prefix) atomicAdd(&myhist[(v[i] >> shift) & dmask], 1u);
+            if ((v[i] & mask) == prefix) atomicAdd(&hist[(v[i] >> shift) & dmask], 1u);
         __syncthreads();
         uint32_t cnts[8];
         uint32_t tot = 0;
@@ -946,11 +935,8 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
             cnts[k] = 0;
             if (k < per) {
                 const int bin = (int)threadIdx.x * per + k;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) {
-                    cnts[k] += hist[c][bin];
-                    hist[c][bin] = 0;
-                }
+                cnts[k] = hist[bin];
+                hist[bin] = 0;
                 tot += cnts[k];
             }
         }
@@ -982,7 +968,49 @@ __global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size
         mask |= dmask << shift;
         rank = s_rank;
     }
-    if (threadIdx.x == 0) med[blockIdx.y * med_stride + b] = __uint_as_float(prefix);
+    return __uint_as_float(prefix);
+}
+
+// The values of block b (bins [1 + bW, 1 + bW + n_b)): thread t holds bins
+// t + NT i; absent entries get the largest key, which never matches a prefix
+// of a real one.  Returns n_b.
+template <int VPT>
+__device__ __forceinline__ int load_block(const float* __restrict__ Ps, int64_t M, int W, int b, uint32_t (&v)[VPT])
+{
+    const int64_t start = 1 + (int64_t)b * W;
+    const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
+#pragma unroll
+    for (int i = 0; i < VPT; ++i) {
+        const int q = (int)threadIdx.x + i * NT;
+        v[i] = q < cnt ? __float_as_uint(Ps[start + q]) : 0xffffffffu;
+    }
+    return cnt;
+}
+
+// Whitening block medians: element of rank floor((n_b-1)/2) of bins
+// [1 + bW, 1 + bW + n_b), by radix selection on the IEEE bits (powers are
+// non-negative, so unsigned order is numeric order).  Three digits: bits
+// 30..20 (the exponent and three mantissa bits, so that the few exponents a
+// block spans spread over many histogram bins), then 19..10 and 9..0.  The
+// block's values stay in registers (VPT per thread).  Counting uses LDS
+// atomics into one histogram (copies per wave measured slower: the smaller
+// LDS footprint and clearing outweigh the extra contention); thread t owns
+// the NBIN/NT consecutive bins from t NBIN/NT on, sums and clears them, and a
+// block-wide prefix sum over the threads finds the digit holding the rank.
+template <int VPT>
+__global__ __launch_bounds__(NT) void k_median(const float* __restrict__ P, size_t p_stride, int64_t M, int W,
+                                               float* __restrict__ med, size_t med_stride)
+{
+    __shared__ uint32_t hist[MED_BINS];
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t s_digit, s_rank;
+    uint32_t v[VPT];
+    const int cnt = load_block<VPT>(P + blockIdx.y * p_stride, M, W, blockIdx.x, v);
+#pragma unroll
+    for (int i = 0; i < MED_BINS / NT; ++i) hist[threadIdx.x + i * NT] = 0;
+    __syncthreads();
+    const float m = block_median<VPT>(v, cnt, hist, wsum, s_digit, s_rank);
+    if (threadIdx.x == 0) med[blockIdx.y * med_stride + blockIdx.x] = m;
 }
 
 // Whitening: P^_k = P_k ln2 / m(k), m the straight line between neighbouring
@@ -1000,7 +1028,10 @@ struct WhitenLine {
     }
 };
 
-__device__ __forceinline__ WhitenLine whiten_line(const float* __restrict__ md, int b, int Mi, int W, int nblk)
+// The line of block b from its own median and its neighbours' (m_l, m_r are
+// not used where block b is the first or the last).
+__device__ __forceinline__ WhitenLine whiten_line_of(int b, int Mi, int W, int nblk, float m_l, float m_here,
+                                                     float m_r)
 {
     auto two_c = [&](int bb) -> int {
         const int n_b = (bb == nblk - 1) ? (Mi - bb * W) : W;
@@ -1010,17 +1041,24 @@ __device__ __forceinline__ WhitenLine whiten_line(const float* __restrict__ md, 
     L.start = 1 + b * W;
     L.cnt = (Mi - b * W) < W ? (Mi - b * W) : W;
     const int c_here = two_c(b);
-    L.m_here = md[b];
+    L.m_here = m_here;
     // left segment [c_{b-1}, c_b), right [c_b, c_{b+1}); flat outside the first/last centre
     const bool has_l = b > 0, has_r = b + 1 < nblk;
     const int c_l = has_l ? two_c(b - 1) : c_here, c_r = has_r ? two_c(b + 1) : c_here;
-    const float m_l = has_l ? md[b - 1] : L.m_here, m_r = has_r ? md[b + 1] : L.m_here;
+    if (!has_l) m_l = m_here;
+    if (!has_r) m_r = m_here;
     L.s_l = has_l ? (L.m_here - m_l) / (float)(c_here - c_l) : 0.0f;
     L.s_r = has_r ? (m_r - L.m_here) / (float)(c_r - c_here) : 0.0f;
     L.base_l = has_l ? (float)c_l : (float)c_here;
     L.ml0 = has_l ? m_l : L.m_here;
     L.fc = (float)c_here;
     return L;
+}
+
+__device__ __forceinline__ WhitenLine whiten_line(const float* __restrict__ md, int b, int Mi, int W, int nblk)
+{
+    const float m_l = b > 0 ? md[b - 1] : 0.0f, m_r = b + 1 < nblk ? md[b + 1] : 0.0f;
+    return whiten_line_of(b, Mi, W, nblk, m_l, md[b], m_r);
 }
 
 constexpr float LN2F = 0.69314718055994530942f;
@@ -1038,36 +1076,75 @@ __device__ __forceinline__ int first_zap(const int2* __restrict__ zap, int nzap,
     return lo;
 }
 
-// Per template, in place.  Bins inside one of the series' birdie ranges
-// (inclusive [x, y], sorted and disjoint) are set to 0; each thread's bins
-// ascend, so its range pointer only moves forward.
-__global__ __launch_bounds__(NT) void k_whiten(float* __restrict__ P, size_t p_stride, int64_t M, int W, int nblk,
-                                               const float* __restrict__ med, size_t med_stride,
-                                               const int2* __restrict__ zap, int nzap)
+// Block medians and whitening in one pass over the spectrum: power P in,
+// whitened power Q out (a separate array: neighbouring workgroups read the
+// raw power of the blocks next to theirs).  Workgroup g owns the mw
+// consecutive blocks [b0, b1) of one template and walks them in order with
+// two blocks' values in registers: the median of block b + 1 is taken, then
+// block b (still in registers) is whitened with the line through the medians
+// of b - 1, b and b + 1 and stored.  The medians of the blocks just outside
+// [b0, b1) are recomputed here rather than waited for (two extra medians per
+// mw blocks), so workgroups never wait on each other.  The medians
+// are k_median's; each bin is whitened as P^ = P ln2 rcp(m(k)), m(k) the line
+// of WhitenLine (0 where m(k) <= 0, in birdie ranges, and at k = 0).  A
+// median pass followed by a separate whitening pass, which reads the spectrum
+// twice, was measured slower.
+template <int VPT>
+__global__ __launch_bounds__(NT) void k_median_whiten(const float* __restrict__ P, float* __restrict__ Q,
+                                                      size_t p_stride, int64_t M, int W, int nblk, int mw,
+                                                      float* __restrict__ med, size_t med_stride,
+                                                      const int2* __restrict__ zap, int nzap)
 {
-    const int b = blockIdx.x;
-    float* Ps = P + blockIdx.y * p_stride;
-    const WhitenLine L = whiten_line(med + blockIdx.y * med_stride, b, (int)M, W, nblk);
-    if (nzap == 0) {
-#pragma unroll 4
-        for (int i = threadIdx.x; i < L.cnt; i += NT) {
-            const int q = L.start + i;
-            const float level = L.level(q);
-            const float p = Ps[q];
-            Ps[q] = level > 0.0f ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
-        }
-    } else {
-        int r = first_zap(zap, nzap, L.start);
-        for (int i = threadIdx.x; i < L.cnt; i += NT) {
-            const int q = L.start + i;
-            while (r < nzap && zap[r].y < q) ++r;
-            const bool zapped = r < nzap && zap[r].x <= q;
-            const float level = L.level(q);
-            const float p = Ps[q];
-            Ps[q] = (level > 0.0f && !zapped) ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
-        }
+    __shared__ uint32_t hist[MED_BINS];
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t s_digit, s_rank;
+    const float* Ps = P + blockIdx.y * p_stride;
+    float* Qs = Q + blockIdx.y * p_stride;
+    float* md = med + blockIdx.y * med_stride;
+    const int b0 = (int)blockIdx.x * mw, b1 = min(b0 + mw, nblk);
+#pragma unroll
+    for (int i = 0; i < MED_BINS / NT; ++i) hist[threadIdx.x + i * NT] = 0;
+    __syncthreads();
+    uint32_t cur[VPT], nxt[VPT];
+    float m_l = 0.0f;
+    if (b0 > 0) {
+        const int c = load_block<VPT>(Ps, M, W, b0 - 1, nxt);
+        m_l = block_median<VPT>(nxt, c, hist, wsum, s_digit, s_rank);
     }
-    if (b == 0 && threadIdx.x == 0) Ps[0] = 0.0f;
+    int cnt = load_block<VPT>(Ps, M, W, b0, cur);
+    float m_c = block_median<VPT>(cur, cnt, hist, wsum, s_digit, s_rank);
+    for (int b = b0; b < b1; ++b) {
+        float m_r = 0.0f;
+        int cnt_n = 0;
+        if (b + 1 < nblk) {
+            cnt_n = load_block<VPT>(Ps, M, W, b + 1, nxt);
+            m_r = block_median<VPT>(nxt, cnt_n, hist, wsum, s_digit, s_rank);
+        }
+        if (threadIdx.x == 0) md[b] = m_c;
+        const WhitenLine L = whiten_line_of(b, (int)M, W, nblk, m_l, m_c, m_r);
+        int r = nzap ? first_zap(zap, nzap, L.start) : 0;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) {
+            const int qi = (int)threadIdx.x + i * NT;
+            if (qi < cnt) {
+                const int q = L.start + qi;
+                bool zapped = false;
+                if (nzap) {
+                    while (r < nzap && zap[r].y < q) ++r;
+                    zapped = r < nzap && zap[r].x <= q;
+                }
+                const float level = L.level(q);
+                const float p = __uint_as_float(cur[i]);
+                Qs[q] = (level > 0.0f && !zapped) ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
+            }
+        }
+        if (b == 0 && threadIdx.x == 0) Qs[0] = 0.0f;
+        m_l = m_c;
+        m_c = m_r;
+        cnt = cnt_n;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) cur[i] = nxt[i];
+    }
 }
 
 // Zeroes the bins of the birdie ranges in a series' whitening factors; one
@@ -1079,8 +1156,8 @@ __global__ __launch_bounds__(NT) void k_zap_factors(float* __restrict__ fac, con
 }
 
 // Once per series: the factor ln2 / m(k) (0 where m(k) <= 0, and at k = 0)
-// that pass 2 applies to every template's power, the same float k_whiten
-// multiplies by.
+// that pass 2 applies to every template's power, the same float the
+// per-template whitening multiplies by.
 __global__ __launch_bounds__(NT) void k_series_factor(const float* __restrict__ med, int64_t M, int W, int nblk,
                                                       float* __restrict__ fac)
 {
@@ -1410,21 +1487,30 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
             hipSuccess)
         return e;
     if (!fac) {
+        // block medians and whitening in one kernel (the whitening class of
+        // the profile then has no launches of its own)
         if ((e = mark(marks, K_MEDIAN, s)) != hipSuccess) return e;
-        if ((e = launch_median(g, nslots, ws, ws.med, ws.med_stride, s)) != hipSuccess) return e;
-        if ((e = mark(marks, K_WHITEN, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_whiten, dim3(g.nblk, nslots), dim3(NT), 0, s, ws.P, ws.p_stride, g.M, g.W, g.nblk,
-                           ws.med, ws.med_stride, zap, nzap);
+        // 8 blocks per workgroup (a quarter more medians than blocks), fewer
+        // when that would leave under about 2048 workgroups
+        const int mw = std::max(2, std::min(8, g.nblk * nslots / 2048));
+        const dim3 grid((g.nblk + mw - 1) / mw, nslots);
+        if (g.W <= 16 * NT)
+            hipLaunchKernelGGL((k_median_whiten<16>), grid, dim3(NT), 0, s, ws.P, ws.Q, ws.p_stride, g.M, g.W,
+                               g.nblk, mw, ws.med, ws.med_stride, zap, nzap);
+        else
+            hipLaunchKernelGGL((k_median_whiten<32>), grid, dim3(NT), 0, s, ws.P, ws.Q, ws.p_stride, g.M, g.W,
+                               g.nblk, mw, ws.med, ws.med_stride, zap, nzap);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = mark(marks, K_HARMSUM, s)) != hipSuccess) return e;
+    const float* spec = fac ? ws.P : ws.Q;  // whitened power
     dim3 hg(g.hgrid, nslots);
     switch (pp.nfold) {
-    case 1: hipLaunchKernelGGL((k_harmsum<1>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
-    case 2: hipLaunchKernelGGL((k_harmsum<2>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
-    case 3: hipLaunchKernelGGL((k_harmsum<3>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
-    case 4: hipLaunchKernelGGL((k_harmsum<4>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
-    case 5: hipLaunchKernelGGL((k_harmsum<5>), hg, dim3(NT), 0, s, ws.P, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 1: hipLaunchKernelGGL((k_harmsum<1>), hg, dim3(NT), 0, s, spec, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 2: hipLaunchKernelGGL((k_harmsum<2>), hg, dim3(NT), 0, s, spec, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 3: hipLaunchKernelGGL((k_harmsum<3>), hg, dim3(NT), 0, s, spec, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 4: hipLaunchKernelGGL((k_harmsum<4>), hg, dim3(NT), 0, s, spec, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
+    case 5: hipLaunchKernelGGL((k_harmsum<5>), hg, dim3(NT), 0, s, spec, ws.p_stride, g.M, tmpl_base, pp, ring, counter, ins.sums, g.tile_of); break;
     default: return hipErrorInvalidValue;
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
