@@ -183,7 +183,7 @@ tb_status tb_search_templates(tb_plan_t plan, int32_t series_id, const tb_templa
  * and the plan's tables (the templates, the FFT exchange buffer, powers,
  * block medians, delay polynomials, the candidate counter and a ring of
  * capacity records) is carved from one fixed device array of
- * TB_NOALLOC_SCRATCH_BYTES (128 MiB) per GPU, set up when the first plan on
+ * TB_NOALLOC_SCRATCH_BYTES (160 MiB) per GPU, set up when the first plan on
  * that GPU is created and held until the process ends (not counted by
  * tb_memory).  The work runs on the plan's first lane; templates per launch
  * are reduced (down to one) until the workspace fits.  Returns when the
@@ -191,12 +191,12 @@ tb_status tb_search_templates(tb_plan_t plan, int32_t series_id, const tb_templa
  * sorted by (series, template, log2_harm, bin), and *n_total holds the
  * exact count.  TB_ERR_TOO_LARGE if count templates, capacity ring records
  * and one template's workspace exceed the array (the workspace alone takes
- * about 96 MiB at 2^24 samples); TB_ERR_OVERFLOW if more than capacity
+ * about 128 MiB at 2^24 samples); TB_ERR_OVERFLOW if more than capacity
  * candidates were found (the first capacity found are returned); otherwise
  * the errors of tb_search_templates.  Every call on one GPU shares that
  * GPU's array, which keeps the last call's contents: calls that overlap on
  * one GPU (from different plans or host threads) race. */
-enum { TB_NOALLOC_SCRATCH_BYTES = 128 << 20 };
+enum { TB_NOALLOC_SCRATCH_BYTES = 160 << 20 };
 tb_status tb_search_templates_noalloc(tb_plan_t plan, int32_t series_id, const tb_template* t, uint32_t count,
                                       uint32_t first_template_id, tb_candidate* out, uint64_t capacity,
                                       uint64_t* n_total);

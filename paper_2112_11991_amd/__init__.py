@@ -26,7 +26,7 @@ TB_ERR_OVERFLOW = -5
 TB_ERR_NOT_READY = -6
 TB_ERR_UNKNOWN_ID = -7
 TB_ERR_TOO_LARGE = -8
-TB_NOALLOC_SCRATCH_BYTES = 128 << 20  # fixed device scratch of tb_search_templates_noalloc, per GPU
+TB_NOALLOC_SCRATCH_BYTES = 160 << 20  # fixed device scratch of tb_search_templates_noalloc, per GPU
 TB_MEM_HOST = 0
 TB_MEM_DEVICE = 1
 TB_SERIES_WHITENING = 2  # OR into the load flags: whiten once from the series' own spectrum

@@ -58,11 +58,30 @@ def test_noalloc_matches_search(tb):
         with pytest.raises(tb.TbError) as e:
             plan.search_noalloc(s1, t1, capacity=7)
         assert e.value.status == tb.TB_ERR_OVERFLOW
-        # more templates than the scratch holds: refused before any work
-        many = np.repeat(t2[:1], 600000)
+        # more templates than the scratch holds (each takes 248 bytes there): refused
+        # before any work
+        many = np.repeat(t2[:1], tb.TB_NOALLOC_SCRATCH_BYTES // 200)
         with pytest.raises(tb.TbError) as e:
             plan.search_noalloc(s2, many)
         assert e.value.status == tb.TB_ERR_TOO_LARGE
         # the plan still works afterwards
         again, _ = plan.search_noalloc(s2, t2, first_template_id=77)
         assert np.array_equal(again, ref2)
+
+
+def test_noalloc_largest_series(tb):
+    """A 2^24-sample series, the longest a plan takes: one template's
+    workspace (about 128 MiB) fits the fixed scratch; results equal
+    tb_search_templates'."""
+    n, ts = 1 << 24, 256e-6
+    rng = np.random.default_rng(7008)
+    orb = synth.Orbit(8 * 3600.0, 3.0, 1.0, 0.08, 2.0)
+    x = synth.inject(rng.standard_normal(n), synth.pulse_train(n, ts, 0.03, 0.05, orb), 20.0).astype(np.float32)
+    tms = np.concatenate([orb.as_template(), synth.uniform_templates(rng, 2, (5.0, 20.0), (0.0, 6.0), ecc_max=0.1)])
+    _say("noalloc: 2^24 x 3 templates")
+    with tb.Plan(threshold_sigma=5.0) as plan:
+        sid = plan.load_series(x, ts)
+        ref = plan.search(sid, tms)
+        got, n_tot = plan.search_noalloc(sid, tms)
+    _say("  candidates %d" % n_tot)
+    assert n_tot == len(ref) > 0 and np.array_equal(got, ref)
