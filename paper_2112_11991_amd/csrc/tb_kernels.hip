@@ -287,11 +287,31 @@ __device__ __forceinline__ constexpr int twst_offset(int NS) { return 15 * (NS -
 constexpr int TWST_RECORDS = 15 * (2 + 4 + 8 + 16);  // record tables of NS = 2..16
 __device__ __forceinline__ constexpr int twpow_offset(int NS) { return TWST_RECORDS + 16 * (NS - 32); }
 
+// W_32^r = exp(-2 pi i r / 32), r < 16, as the host's FP64-built stage table
+// rounds them to FP32 (the entry for r = 8 keeps cos's 6.1e-17).
+__device__ constexpr float kW32c[16] = {
+    1.0f, 0.9807852506637573f, 0.9238795042037964f, 0.8314695954322815f, 0.7071067690849304f,
+    0.5555702447891235f, 0.3826834261417389f, 0.19509032368659973f, 6.123234262925839e-17f,
+    -0.19509032368659973f, -0.3826834261417389f, -0.5555702447891235f, -0.7071067690849304f,
+    -0.8314695954322815f, -0.9238795042037964f, -0.9807852506637573f};
+__device__ constexpr float kW32s[16] = {
+    -0.0f, -0.19509032368659973f, -0.3826834261417389f, -0.5555702447891235f, -0.7071067690849304f,
+    -0.8314695954322815f, -0.9238795042037964f, -0.9807852506637573f, -1.0f, -0.9807852506637573f,
+    -0.9238795042037964f, -0.8314695954322815f, -0.7071067690849304f, -0.5555702447891235f,
+    -0.3826834261417389f, -0.19509032368659973f};
+
 // Stage twiddles of a radix-16 Stockham stage of stride NS: v[r] *= W_{16 NS}^{r k}.
+// Stride 2 has k in {0, 1}, whose twiddles are 1 and the constants above: no
+// table loads to wait for after the stage's barrier.
 template <int RAD, int NS>
 __device__ __forceinline__ void stage_twiddle(float2* v, const float2* __restrict__ twst, int k)
 {
-    if (NS > 1 && NS < 32) {
+    if (NS == 2) {
+        const bool odd = (k & 1) != 0;
+#pragma unroll
+        for (int r = 1; r < RAD; ++r)
+            v[r] = cmul(v[r], odd ? make_float2(kW32c[r], kW32s[r]) : make_float2(1.0f, -0.0f));
+    } else if (NS > 1 && NS < 32) {
         const float2* tw = twst + twst_offset(NS) + 15 * k;
 #pragma unroll
         for (int r = 1; r < RAD; ++r) v[r] = cmul(v[r], tw[r - 1]);
