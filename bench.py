@@ -264,7 +264,7 @@ def bank_report(tb, with_oracle: bool):
         for name, kind, count, emax in (("circular", tb.TB_BANK_CIRCULAR, 1 << 20, 0.0),
                                         ("elliptical", tb.TB_BANK_ELLIPTICAL, 1 << 18, 0.1)):
             pr = bank.Priors(porb_s=(6 * 3600.0, 12 * 3600.0), ecc_max=emax)
-            pts, _ = bank._draw(kind, pr, rng, count)
+            pts, _, _ = bank.proposals(plan, kind, T, f, pr, rng, count)
             plan.bank_density(kind, T, f, pts[:4096])
             _, ms = plan.bank_density(kind, T, f, pts)
             rec = {"points": count, "kernel_ms": ms, "value": count / (ms * 1e-3)}

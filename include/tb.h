@@ -334,6 +334,39 @@ typedef struct {
 tb_status tb_bank_density(tb_plan_t plan, const tb_bank_metric* m, const tb_template* points, uint64_t count,
                           double* out, double* kernel_ms);
 
+/* Prior region of a random bank (Table 1): P_orb uniform in [porb_min_s, porb_max_s]; tau uniform below the
+ * Kepler limit tau_max(P_orb) = (G M_sun / c^3)^(1/3) (2 pi / P_orb)^(-2/3) m_c / (m_p + m_c)^(2/3) lt-s for a
+ * pulsar of at least m_pulsar_min_msun and a companion of at most m_comp_max_msun solar masses (Sec. 2.7); alpha
+ * (and psi) uniform in [0, 2 pi); e uniform in [0, ecc_max) (elliptical banks, ecc_max > 0). */
+typedef struct {
+    double porb_min_s, porb_max_s;
+    double m_pulsar_min_msun, m_comp_max_msun;
+    double ecc_max;
+} tb_bank_priors;
+
+/* Proposals of a random bank (Secs. 2.5-2.7): maps count rows of uniform draws u (host, row-major, d = 3
+ * values in [0, 1) per row for TB_BANK_CIRCULAR, d = 5 for TB_BANK_ELLIPTICAL, in the order P_orb, tau / tau_max,
+ * alpha, e, psi) to points of the prior region, takes their proper-volume densities as tb_bank_density does, and
+ * weighs each by density / proposal pdf.  points and weights (host, count entries) may be NULL.  stats[0] receives
+ * the Monte-Carlo volume (the mean weight: the integral of the density over the region), stats[1] its standard
+ * error, stats[2] the largest weight.  The caller draws u, so banks are reproducible from its generator.
+ * TB_ERR_INVALID_ARG for a bad metric (as tb_bank_density) or priors (porb_min_s <= 0 or > porb_max_s, masses
+ * <= 0, ecc_max outside (0, 1) for elliptical banks), count < 2 with stats. */
+tb_status tb_bank_propose(tb_plan_t plan, const tb_bank_metric* m, const tb_bank_priors* priors, const double* u,
+                          uint64_t count, tb_template* points, double* weights, double* stats, double* kernel_ms);
+
+/* Number of random templates for coverage eta and maximal mismatch mu in a bank of proper volume V and dimension
+ * n (Sec. 2.7): ln(1 - eta) / ln(1 - mu^(n/2) C_n / V), C_n = pi^(n/2) / Gamma(n/2 + 1) the volume of the unit
+ * n-ball.  TB_ERR_INVALID_ARG unless V > 0, 0 < eta < 1, mu > 0, 1 <= n <= 16 and mu^(n/2) C_n < V. */
+tb_status tb_bank_count(double volume, uint32_t n, double coverage, double mismatch, double* count);
+
+/* Rejection step of the random bank: proposal i is kept (keep[i] = 1) when u[i] * wmax < weights[i], so kept
+ * points are distributed as the density (Sec. 2.5).  *n_keep (may be NULL) receives the number kept, *n_above
+ * (may be NULL) the number of weights above wmax (kept regardless; a scale that is too small shows there).
+ * Host arrays of count entries.  TB_ERR_INVALID_ARG for NULL arrays with count > 0 or wmax <= 0. */
+tb_status tb_bank_select(const double* weights, const double* u, uint64_t count, double wmax, uint8_t* keep,
+                         uint64_t* n_keep, uint64_t* n_above);
+
 /* Candidate grouping (App. A: the search software groups repeated detections
  * of the same signal and keeps the strongest; the paper gives no rule, this
  * is the library's).  Host arrays, no plan or device needed.

@@ -88,12 +88,17 @@ EXPORTS = [
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
     "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density", "tb_dedisperse", "tb_set_shape",
-    "tb_search_templates_noalloc",
+    "tb_search_templates_noalloc", "tb_bank_propose", "tb_bank_count", "tb_bank_select",
 ]
 
 
 class TbBankMetric(C.Structure):
     _fields_ = [("kind", C.c_uint32), ("nodes", C.c_uint32), ("tobs_s", C.c_double), ("fmax_hz", C.c_double)]
+
+
+class TbBankPriors(C.Structure):
+    _fields_ = [("porb_min_s", C.c_double), ("porb_max_s", C.c_double), ("m_pulsar_min_msun", C.c_double),
+                ("m_comp_max_msun", C.c_double), ("ecc_max", C.c_double)]
 
 
 class TbFilterbank(C.Structure):
@@ -150,6 +155,9 @@ def _load():
     L.tb_set_shape.argtypes = [vp, u32, u32, u32]
     L.tb_bank_density.argtypes = [vp, P(TbBankMetric), vp, u64, vp, P(C.c_double)]
     L.tb_dedisperse.argtypes = [vp, P(TbFilterbank), vp, u32, vp, u32, vp, P(u64), P(C.c_double)]
+    L.tb_bank_propose.argtypes = [vp, P(TbBankMetric), P(TbBankPriors), vp, u64, vp, vp, vp, P(C.c_double)]
+    L.tb_bank_count.argtypes = [C.c_double, u32, C.c_double, C.c_double, P(C.c_double)]
+    L.tb_bank_select.argtypes = [vp, vp, u64, C.c_double, vp, P(u64), P(u64)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tb_default_config", "tb_strerror"):
@@ -317,6 +325,40 @@ def tb_bank_density(plan: int, kind: int, tobs_s: float, fmax_hz: float, points,
     return out[: pts.size], ms.value
 
 
+def tb_bank_propose(plan: int, kind: int, tobs_s: float, fmax_hz: float, priors: TbBankPriors, u,
+                    nodes: int = 128):
+    """Maps uniform draws u (count x 3 circular, x 5 elliptical) to prior points:
+    (points, weights density/pdf, (volume, standard error, largest weight), kernel ms)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    count = u.shape[0]
+    pts = np.zeros(count, dtype=TEMPLATE_DTYPE)
+    w = np.zeros(count, dtype=np.float64)
+    st = np.zeros(3, dtype=np.float64)
+    ms = C.c_double(0.0)
+    m = TbBankMetric(int(kind), int(nodes), float(tobs_s), float(fmax_hz))
+    _check(_L.tb_bank_propose(None if plan is None else C.c_void_p(plan), C.byref(m), C.byref(priors), _ptr(u),
+                              count, _ptr(pts), _ptr(w), _ptr(st) if count > 1 else None, C.byref(ms)),
+           "tb_bank_propose")
+    return pts, w, (float(st[0]), float(st[1]), float(st[2])), ms.value
+
+
+def tb_bank_count(volume: float, n: int, coverage: float, mismatch: float) -> float:
+    out = C.c_double(0.0)
+    _check(_L.tb_bank_count(float(volume), int(n), float(coverage), float(mismatch), C.byref(out)), "tb_bank_count")
+    return out.value
+
+
+def tb_bank_select(weights, u, wmax: float):
+    """(indices kept, number kept, number of weights above wmax)."""
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    keep = np.zeros(w.size, dtype=np.uint8)
+    nk, na = C.c_uint64(0), C.c_uint64(0)
+    _check(_L.tb_bank_select(_ptr(w), _ptr(u), w.size, float(wmax), _ptr(keep), C.byref(nk), C.byref(na)),
+           "tb_bank_select")
+    return np.flatnonzero(keep), nk.value, na.value
+
+
 def tb_dedisperse(plan: int, data, fch1_mhz: float, foff_mhz: float, tsamp_s: float, dms, out=None,
                   nchan: int | None = None, nsamp: int | None = None, nbits: int = 8):
     """data: uint8 (nsamp, nchan) numpy array of 8-bit samples (or, nbits = 4,
@@ -437,6 +479,9 @@ class Plan:
 
     def bank_density(self, kind, tobs_s, fmax_hz, points, nodes=128):
         return tb_bank_density(self.handle, kind, tobs_s, fmax_hz, points, nodes)
+
+    def bank_propose(self, kind, tobs_s, fmax_hz, priors, u, nodes=128):
+        return tb_bank_propose(self.handle, kind, tobs_s, fmax_hz, priors, u, nodes)
 
     def dedisperse(self, data, fch1_mhz, foff_mhz, tsamp_s, dms, out=None, nchan=None, nsamp=None, nbits=8):
         return tb_dedisperse(self.handle, data, fch1_mhz, foff_mhz, tsamp_s, dms, out, nchan, nsamp, nbits)

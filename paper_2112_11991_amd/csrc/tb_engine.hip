@@ -1026,6 +1026,91 @@ tb_status tb_bank_density(tb_plan_t p, const tb_bank_metric* m, const tb_templat
     return st;
 }
 
+tb_status tb_bank_propose(tb_plan_t p, const tb_bank_metric* m, const tb_bank_priors* pr, const double* u,
+                          uint64_t count, tb_template* points, double* weights, double* stats, double* kernel_ms)
+{
+    if (!p || !m || !pr || (count && !u) || (stats && count < 2) || count > (1ull << 31)) return TB_ERR_INVALID_ARG;
+    const bool ell = m->kind == TB_BANK_ELLIPTICAL;
+    if (!(pr->porb_min_s > 0.0) || !(pr->porb_max_s >= pr->porb_min_s) || !std::isfinite(pr->porb_max_s) ||
+        !(pr->m_pulsar_min_msun > 0.0) || !(pr->m_comp_max_msun > 0.0) || !std::isfinite(pr->m_pulsar_min_msun) ||
+        !std::isfinite(pr->m_comp_max_msun) || (ell && !(pr->ecc_max > 0.0 && pr->ecc_max < 1.0)))
+        return TB_ERR_INVALID_ARG;
+    const int d = ell ? 5 : 3;
+    for (uint64_t i = 0; i < count * (uint64_t)d; ++i)
+        if (!(u[i] >= 0.0 && u[i] < 1.0)) return TB_ERR_INVALID_ARG;
+    // G M_sun / c^3 [s]
+    const double tsun = 4.925490947e-6;
+    const double span = pr->porb_max_s - pr->porb_min_s;
+    std::vector<tb_template> pts((size_t)count);
+    std::vector<double> pdf((size_t)count), dens((size_t)count);
+    for (uint64_t i = 0; i < count; ++i) {
+        const double* ui = u + (size_t)i * d;
+        tb_template& t = pts[(size_t)i];
+        t.porb_s = pr->porb_min_s + span * ui[0];
+        const double om = 2.0 * kPi / t.porb_s;
+        const double tau_max = std::cbrt(tsun) * std::pow(om, -2.0 / 3.0) * pr->m_comp_max_msun /
+                               std::pow(pr->m_pulsar_min_msun + pr->m_comp_max_msun, 2.0 / 3.0);
+        t.tau_lts = ui[1] * tau_max;
+        t.alpha_rad = 2.0 * kPi * ui[2];
+        double q = 1.0 / ((span > 0.0 ? span : 1.0) * tau_max * 2.0 * kPi);
+        t.ecc = 0.0;
+        t.omega_rad = 0.0;
+        if (ell) {
+            t.ecc = pr->ecc_max * ui[3];
+            t.omega_rad = 2.0 * kPi * ui[4];
+            q /= pr->ecc_max * 2.0 * kPi;
+        }
+        pdf[(size_t)i] = q;
+    }
+    tb_status st = tb_bank_density(p, m, pts.data(), count, dens.data(), kernel_ms);
+    if (st) return st;
+    double sw = 0.0, sw2 = 0.0, wmax = 0.0;
+    for (uint64_t i = 0; i < count; ++i) {
+        const double w = dens[(size_t)i] / pdf[(size_t)i];
+        if (weights) weights[i] = w;
+        sw += w;
+        sw2 += w * w;
+        wmax = std::max(wmax, w);
+    }
+    if (points) std::memcpy(points, pts.data(), sizeof(tb_template) * (size_t)count);
+    if (stats) {
+        const double n = (double)count, mean = sw / n;
+        const double var = std::max(0.0, (sw2 - n * mean * mean) / (n - 1.0));
+        stats[0] = mean;
+        stats[1] = std::sqrt(var / n);
+        stats[2] = wmax;
+    }
+    return TB_OK;
+}
+
+tb_status tb_bank_count(double volume, uint32_t n, double coverage, double mismatch, double* count)
+{
+    if (!count || !(volume > 0.0) || !std::isfinite(volume) || !(coverage > 0.0 && coverage < 1.0) ||
+        !(mismatch > 0.0) || !std::isfinite(mismatch) || n < 1 || n > 16)
+        return TB_ERR_INVALID_ARG;
+    const double h = 0.5 * (double)n;
+    const double cn = std::pow(kPi, h) / std::tgamma(h + 1.0);
+    const double x = std::pow(mismatch, h) * cn / volume;
+    if (!(x < 1.0)) return TB_ERR_INVALID_ARG;
+    *count = std::log(1.0 - coverage) / std::log1p(-x);
+    return TB_OK;
+}
+
+tb_status tb_bank_select(const double* weights, const double* u, uint64_t count, double wmax, uint8_t* keep,
+                         uint64_t* n_keep, uint64_t* n_above)
+{
+    if ((count && (!weights || !u || !keep)) || !(wmax > 0.0) || !std::isfinite(wmax)) return TB_ERR_INVALID_ARG;
+    uint64_t k = 0, a = 0;
+    for (uint64_t i = 0; i < count; ++i) {
+        keep[i] = (uint8_t)(u[i] * wmax < weights[i]);
+        k += keep[i];
+        a += weights[i] > wmax;
+    }
+    if (n_keep) *n_keep = k;
+    if (n_above) *n_above = a;
+    return TB_OK;
+}
+
 tb_status tb_set_shape(tb_plan_t p, uint32_t log2n, uint32_t tile_points, uint32_t batch_templates)
 {
     if (!p || log2n < 10 || log2n > p->cfg.max_log2n ||

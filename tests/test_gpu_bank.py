@@ -80,7 +80,7 @@ def test_circular_bank_size_of_the_paper(tb):
     _say("circular bank: %s" % info)
     assert abs(info["count"] - 10128) <= 3 * info["volume_err"] / info["volume"] * info["count"] + 1
     assert tm.size == info["count"]
-    lim = bank.kepler_tau_limit(tm["porb_s"], 1.4, 8.0)
+    lim = obank.tau_max(tm["porb_s"], 1.4, 8.0)
     assert np.all((tm["porb_s"] >= 6 * HOUR) & (tm["porb_s"] <= 12 * HOUR) & (tm["tau_lts"] <= lim))
     assert info["above_scale"] < 1e-3 * info["proposals"]
 
@@ -105,3 +105,47 @@ def test_selection_matches_the_oracle(tb):
     edge = np.abs(u * wmax - do / q) <= 1e-6 * do / q
     assert len(ko) > 100
     assert all(edge[i] for i in kg ^ ko)
+
+
+def test_proposals_against_the_oracle(tb):
+    """tb_bank_propose on given uniform draws: the points are the prior map of
+    Table 1 (P_orb, tau / tau_max, alpha, e, psi), the weights the oracle's
+    density over its proposal pdf, the volume statistics their mean, standard
+    error and maximum.  Circular: the Table 1 orbits (6-12 h over 1.2 h).
+    Elliptical: orbits of 0.4-1 h, so that the observation spans more than an
+    orbit (over a fifth of an orbit the elliptical directions are nearly
+    dependent and FP64 determines the density to ~1e-4 only).  Tolerance per
+    point from its metric's conditioning, as in the density test above."""
+    from paper_2112_11991_amd import bank
+
+    T, f = 1.2 * HOUR, 66.67
+    rng = np.random.default_rng(77)
+    for kind, emax, (p0, p1) in ((0, 0.0, (6 * HOUR, 12 * HOUR)), (1, 0.1, (0.4 * HOUR, 1.0 * HOUR))):
+        pr = bank.Priors(porb_s=(p0, p1), ecc_max=emax)
+        u = bank.uniforms(kind, rng, 3000)
+        with tb.Plan() as plan:
+            pts, w, (vol, err, wmax), _ = plan.bank_propose(kind, T, f, pr.c(), u)
+        P = p0 + (p1 - p0) * u[:, 0]
+        tmax = obank.tau_max(P, 1.4, 8.0)
+        q = 1.0 / ((p1 - p0) * tmax * 2 * math.pi)
+        assert np.allclose(pts["porb_s"], P, rtol=1e-15) and np.allclose(pts["tau_lts"], u[:, 1] * tmax, rtol=1e-13)
+        assert np.allclose(pts["alpha_rad"], 2 * math.pi * u[:, 2], rtol=1e-15)
+        if kind:
+            assert np.allclose(pts["ecc"], emax * u[:, 3], rtol=1e-15)
+            assert np.allclose(pts["omega_rad"], 2 * math.pi * u[:, 4], rtol=1e-15)
+            q = q / (emax * 2 * math.pi)
+        do = obank.density(kind, T, f, pts["porb_s"], pts["tau_lts"], pts["alpha_rad"],
+                           pts["ecc"] if kind else None, pts["omega_rad"] if kind else None, nodes=128)
+        wo = do / q
+        assert np.all(wo > 0)
+        gam = obank.gamma_tilde(kind, T, pts["porb_s"], pts["tau_lts"], pts["alpha_rad"],
+                                pts["ecc"] if kind else None, pts["omega_rad"] if kind else None, nodes=128)
+        dia = np.sqrt(np.einsum("pii->pi", gam))
+        kappa = np.linalg.cond(gam / dia[:, :, None] / dia[:, None, :])
+        rel = np.abs(w / wo - 1.0)
+        tol = 1e-11 + 20 * (3 + 2 * kind) * kappa * np.finfo(np.float64).eps
+        assert np.all(rel <= tol), (kind, (rel / tol).max())
+        vo, eo = obank.volume_mc(do, q)
+        assert abs(vol / vo - 1.0) <= np.sum(tol * wo) / np.sum(wo) and abs(err / eo - 1.0) <= 1e-3
+        assert wmax == w.max()
+        _say("kind %d: volume %.6g (oracle %.6g), stderr %.3g" % (kind, vol, vo, err))
