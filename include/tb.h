@@ -238,6 +238,55 @@ tb_status tb_memory(tb_plan_t plan, uint64_t* held_bytes, uint64_t* budget_bytes
  * later allocations that would exceed the budget fail with TB_ERR_BUDGET. */
 tb_status tb_set_budget(tb_plan_t plan, uint64_t budget_bytes);
 
+/* Continuous-batching service of a request stream (the per-DM-trial x
+ * template workload of Sec. 5 arriving over time; the paper states no
+ * scheduling, so this is the library's own).  Each request is a resident
+ * series and a chunk of templates that becomes available at t_arrival_s
+ * (seconds after the call starts, times time_scale).  The calling thread
+ * admits requests in arrival order as soon as they have arrived and the
+ * plan's HBM budget allows (a request refused with TB_ERR_BUDGET waits for
+ * running ones to finish), lets tb_search_templates spread them over the
+ * plan's lanes, polls the running ones without sleeping and copies each
+ * request's candidates (sorted as by tb_get_candidates) into out the moment
+ * its device work has finished, then releases it.  With TB_SERVE_SATURATE
+ * every request counts as arrived at t = 0.
+ *   req     count requests, any order; templates are read during the call
+ *   out     host array of capacity records shared by all requests, filled in
+ *           completion order; NULL with capacity 0 keeps counts only
+ *   res     host array of count results, in req's order: admission and
+ *           completion times (seconds after the call started), where the
+ *           request's records start in out, how many were copied, the exact
+ *           count, and TB_OK or TB_ERR_OVERFLOW (the device ring or out held
+ *           fewer than the count)
+ *   stats   may be NULL: [0] most requests in flight at once, [1] admissions
+ *           deferred by the budget
+ * TB_ERR_BUDGET if a request does not fit the budget with nothing running;
+ * TB_ERR_INVALID_ARG for bad arguments (checked before anything is queued);
+ * otherwise the first error of an underlying call, after the requests in
+ * flight have been waited for and released. */
+typedef struct {
+    double t_arrival_s;
+    int32_t series_id;
+    uint32_t count;               /* templates */
+    const tb_template* templates; /* host */
+    uint32_t first_template_id;
+    uint32_t reserved;
+} tb_serve_request;
+
+typedef struct {
+    double t_admit_s;
+    double t_done_s;
+    uint64_t cand_offset;
+    uint64_t n_copied;
+    uint64_t n_total;
+    int32_t status;
+    uint32_t reserved;
+} tb_serve_result;
+
+enum { TB_SERVE_SATURATE = 1 };
+tb_status tb_serve(tb_plan_t plan, const tb_serve_request* req, uint32_t count, double time_scale, uint32_t flags,
+                   tb_candidate* out, uint64_t capacity, tb_serve_result* res, uint32_t stats[2]);
+
 /* Static description of a status (a utility; the paper defines nothing here). */
 const char* tb_strerror(tb_status status);
 

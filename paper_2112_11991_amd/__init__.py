@@ -88,8 +88,16 @@ EXPORTS = [
     "tb_poll", "tb_get_candidates", "tb_release", "tb_synchronize", "tb_strerror", "tb_inspect_template",
     "tb_thresholds", "tb_last_request_ms", "tb_profile", "tb_profile_read", "tb_stream_copy", "tb_memory",
     "tb_set_budget", "tb_distill", "tb_zap_series", "tb_bank_density", "tb_dedisperse", "tb_set_shape",
-    "tb_search_templates_noalloc", "tb_bank_propose", "tb_bank_count", "tb_bank_select",
+    "tb_search_templates_noalloc", "tb_bank_propose", "tb_bank_count", "tb_bank_select", "tb_serve",
 ]
+
+# tb_serve_request / tb_serve_result records
+SERVE_REQUEST_DTYPE = np.dtype([("t_arrival_s", "<f8"), ("series_id", "<i4"), ("count", "<u4"),
+                                ("templates", "<u8"), ("first_template_id", "<u4"), ("reserved", "<u4")])
+SERVE_RESULT_DTYPE = np.dtype([("t_admit_s", "<f8"), ("t_done_s", "<f8"), ("cand_offset", "<u8"),
+                               ("n_copied", "<u8"), ("n_total", "<u8"), ("status", "<i4"), ("reserved", "<u4")])
+assert SERVE_REQUEST_DTYPE.itemsize == 32 and SERVE_RESULT_DTYPE.itemsize == 48
+TB_SERVE_SATURATE = 1
 
 
 class TbBankMetric(C.Structure):
@@ -158,6 +166,7 @@ def _load():
     L.tb_bank_propose.argtypes = [vp, P(TbBankMetric), P(TbBankPriors), vp, u64, vp, vp, vp, P(C.c_double)]
     L.tb_bank_count.argtypes = [C.c_double, u32, C.c_double, C.c_double, P(C.c_double)]
     L.tb_bank_select.argtypes = [vp, vp, u64, C.c_double, vp, P(u64), P(u64)]
+    L.tb_serve.argtypes = [vp, vp, u32, C.c_double, u32, vp, u64, vp, vp]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("tb_default_config", "tb_strerror"):
@@ -248,6 +257,26 @@ def tb_search_templates_noalloc(plan: int, series_id: int, templates, first_temp
     if not (st == TB_ERR_OVERFLOW and allow_overflow):
         _check(st, "tb_search_templates_noalloc")
     return out[:min(out.size, int(n.value))], int(n.value)
+
+
+def tb_serve(plan: int, requests, time_scale: float = 1.0, saturate: bool = False, capacity: int = 1 << 20):
+    """Runs a request stream through the library's serving loop.  requests:
+    (t_arrival_s, series_id, templates, first_template_id) tuples.  Returns
+    (results SERVE_RESULT_DTYPE in request order, candidates of all requests
+    in completion order, (most in flight, budget waits)); a request's records
+    are candidates[cand_offset : cand_offset + n_copied]."""
+    tms = [as_templates(r[2]) for r in requests]  # kept alive through the call
+    req = np.zeros(len(requests), dtype=SERVE_REQUEST_DTYPE)
+    for i, (r, a) in enumerate(zip(requests, tms)):
+        req[i] = (float(r[0]), int(r[1]), len(a), a.ctypes.data if a.size else 0, int(r[3]), 0)
+    res = np.zeros(len(requests), dtype=SERVE_RESULT_DTYPE)
+    out = np.zeros(int(capacity), dtype=CANDIDATE_DTYPE)
+    stats = np.zeros(2, dtype=np.uint32)
+    _check(_L.tb_serve(C.c_void_p(plan), _ptr(req), req.size, float(time_scale),
+                       TB_SERVE_SATURATE if saturate else 0, _ptr(out) if out.size else None, out.size,
+                       _ptr(res), _ptr(stats)), "tb_serve")
+    used = int((res["cand_offset"] + res["n_copied"]).max()) if res.size else 0
+    return res, out[:used], (int(stats[0]), int(stats[1]))
 
 
 def tb_poll(plan: int, request_id: int) -> bool:
@@ -510,6 +539,9 @@ class Plan:
 
     def release(self, rid):
         tb_release(self.handle, rid)
+
+    def serve(self, requests, time_scale=1.0, saturate=False, capacity=1 << 20):
+        return tb_serve(self.handle, requests, time_scale, saturate, capacity)
 
     def search(self, sid, templates, first_template_id=0):
         """Submit, wait, fetch and release: the sorted candidate array."""

@@ -1628,3 +1628,5 @@ tb_status tb_inspect_template(tb_plan_t p, int32_t sid, const tb_template* t, in
 }
 
 }  // extern "C"
+
+uint64_t tb::plan_ring_capacity(tb_plan_t p) { return p ? p->cfg.ring_capacity : 0; }

@@ -161,6 +161,8 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s)
 // Rewrites a mean-removed series into the tile order pass 1 reads.
 hipError_t launch_tile_series(const Geometry& g, const float* in, float* out, hipStream_t s);
 int harmsum_tile();
+// Candidate records a request's device ring holds (the plan's ring_capacity).
+uint64_t plan_ring_capacity(tb_plan_t p);
 // Dedispersion: integer delays delay[c * ldd + d] (ldd = ndm rounded up to the
 // DM tile) of every channel and trial; returns the largest.
 int64_t dedisp_delays(int nchan, double fch1, double foff, double tsamp, const double* dm, int ndm,

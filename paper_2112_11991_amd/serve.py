@@ -1,24 +1,22 @@
-"""Continuous-batching request loop over the C ABI.
+"""Request streams through the library's continuous-batching loop (tb_serve).
 
 Requests (a resident series plus a chunk of templates) arrive over time.  The
-loop admits each one as soon as it has arrived and the plan's HBM budget
-allows (tb_search_templates returns TB_ERR_BUDGET otherwise and the request
-waits for completions to free memory), spreads admitted requests over the
-plan's lanes so that their kernels overlap on the device, and collects each
-request's candidates the moment its device work has finished.  Per-request
-latency is arrival -> candidates retrievable.
+library admits each one as soon as it has arrived and the plan's HBM budget
+allows, spreads admitted requests over the plan's lanes so that their kernels
+overlap on the device, and collects each request's candidates the moment its
+device work has finished.  Per-request latency is arrival -> candidates
+retrievable.
 
-Nothing here computes any part of the search: it only orders calls to the
-library.
+This module only builds the request records and reads back the per-request
+results; the loop itself runs in the library.
 """
 from __future__ import annotations
 
-import time
 from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import TB_ERR_BUDGET, Plan, TbError
+from . import TB_ERR_OVERFLOW, Plan
 
 
 @dataclass
@@ -28,11 +26,11 @@ class Request:
     templates: np.ndarray     # TEMPLATE_DTYPE records
     first_template_id: int = 0
     # filled by the loop
-    rid: int | None = None
     t_admit: float | None = None
     t_done: float | None = None
     candidates: np.ndarray | None = None
     n_total: int = 0
+    overflow: bool = False
 
 
 @dataclass
@@ -64,54 +62,21 @@ class ServeReport:
 
 
 def serve(plan: Plan, series_ids: list[int], series_len: list[int], requests: list[Request],
-          realtime: bool = True, poll_s: float = 2e-4, time_scale: float = 1.0) -> ServeReport:
+          realtime: bool = True, time_scale: float = 1.0, capacity: int = 1 << 20) -> ServeReport:
     """Runs the trace to completion.  With realtime=False every request is
     taken as arrived at t = 0 (a saturation run).  time_scale stretches the
-    arrival times (2.0 = half the arrival rate)."""
-    pending = sorted(requests, key=lambda r: r.t_arrival)
-    waiting: list[Request] = []
-    running: list[Request] = []
-    done: list[Request] = []
-    t0 = time.perf_counter()
-    max_in_flight = 0
-    budget_waits = 0
-    i = 0
-    while i < len(pending) or waiting or running:
-        now = time.perf_counter() - t0
-        while i < len(pending) and (not realtime or pending[i].t_arrival * time_scale <= now):
-            waiting.append(pending[i])
-            i += 1
-        # admit in arrival order while memory allows
-        while waiting:
-            r = waiting[0]
-            try:
-                r.rid = plan.submit(series_ids[r.series], r.templates, r.first_template_id)
-            except TbError as e:
-                if e.status != TB_ERR_BUDGET or not running:
-                    raise
-                budget_waits += 1
-                break
-            r.t_admit = time.perf_counter() - t0
-            running.append(waiting.pop(0))
-        max_in_flight = max(max_in_flight, len(running))
-        progressed = False
-        still = []
-        for r in running:
-            if plan.poll(r.rid):
-                r.t_done = time.perf_counter() - t0
-                r.candidates, r.n_total = plan.candidates(r.rid, blocking=True, allow_overflow=True)
-                plan.release(r.rid)
-                done.append(r)
-                progressed = True
-            else:
-                still.append(r)
-        running = still
-        if not progressed and running:
-            time.sleep(poll_s)
-        elif not running and not waiting and i < len(pending) and realtime:
-            time.sleep(max(0.0, min(poll_s * 10, pending[i].t_arrival * time_scale - (time.perf_counter() - t0))))
-    makespan = max(r.t_done for r in done) - (min(r.t_arrival for r in done) * time_scale if realtime else 0.0)
-    lat = np.array([r.t_done - (r.t_arrival * time_scale if realtime else 0.0) for r in done])
-    ntemp = int(sum(len(r.templates) for r in done))
-    work = float(sum(len(r.templates) * series_len[r.series] for r in done))
-    return ServeReport(len(done), ntemp, work, makespan, lat, max_in_flight, budget_waits)
+    arrival times (2.0 = half the arrival rate).  capacity: candidate records
+    kept over the whole trace."""
+    res, cands, (max_in_flight, budget_waits) = plan.serve(
+        [(r.t_arrival, series_ids[r.series], r.templates, r.first_template_id) for r in requests],
+        time_scale=time_scale, saturate=not realtime, capacity=capacity)
+    for r, o in zip(requests, res):
+        r.t_admit, r.t_done = float(o["t_admit_s"]), float(o["t_done_s"])
+        r.candidates = cands[int(o["cand_offset"]):int(o["cand_offset"] + o["n_copied"])]
+        r.n_total, r.overflow = int(o["n_total"]), int(o["status"]) == TB_ERR_OVERFLOW
+    arrival = np.array([r.t_arrival * time_scale if realtime else 0.0 for r in requests])
+    done = res["t_done_s"]
+    makespan = float(done.max() - arrival.min())
+    ntemp = int(sum(len(r.templates) for r in requests))
+    work = float(sum(len(r.templates) * series_len[r.series] for r in requests))
+    return ServeReport(len(requests), ntemp, work, makespan, done - arrival, max_in_flight, budget_waits)

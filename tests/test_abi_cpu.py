@@ -65,3 +65,4 @@ def test_null_plan_calls_are_rejected():
     assert L.tb_release(None, 1) == tb.TB_ERR_INVALID_ARG
     assert L.tb_destroy(None) == tb.TB_OK
     assert L.tb_plan(None, None) == tb.TB_ERR_INVALID_ARG
+    assert L.tb_serve(None, None, 0, 1.0, 0, None, 0, None, None) == tb.TB_ERR_INVALID_ARG

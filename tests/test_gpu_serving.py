@@ -122,3 +122,38 @@ def test_profile_samples_every_kth_wave(tb):
     assert list(launches) == [4, 4, 4, 4, 0, 4]
     assert ntemp == 32
     assert (ms[[0, 1, 2, 3, 5]] > 0).all() and ms[4] == 0
+
+
+def test_serve_realtime_order_and_shared_capacity(tb):
+    """tb_serve on a real-time trace (arrivals 2 ms apart): no request is
+    admitted before it arrives or finishes before it is admitted, and every
+    request's records equal its result alone.  With an output array of half
+    the records, requests are filled in completion order until it is full:
+    each keeps a prefix of its sorted records and those cut short report
+    TB_ERR_OVERFLOW with the exact count."""
+    lens, series = _pool()
+    reqs = _trace(n_req=12, seed=506)
+    ref = _alone(tb, series, reqs)
+    total = sum(r.size for r in ref)
+    with tb.Plan(fmin_hz=2.0, ring_capacity=1 << 16, lanes=2) as plan:
+        sids = [plan.load_series(x, 64e-6) for x in series]
+        rq = [(t, sids[s], tm, first) for t, s, tm, first in reqs]
+        res, cands, (most, waits) = plan.serve(rq)
+        assert waits == 0 and most >= 1
+        arrival = np.array([t for t, *_ in reqs])
+        assert np.all(res["t_admit_s"] >= arrival) and np.all(res["t_done_s"] >= res["t_admit_s"])
+        assert np.all(res["status"] == tb.TB_OK) and cands.size == total
+        for o, a in zip(res, ref):
+            got = cands[int(o["cand_offset"]):int(o["cand_offset"] + o["n_copied"])]
+            assert o["n_total"] == a.size and np.array_equal(got, a)
+
+        cap = total // 2
+        res, cands, _ = plan.serve(rq, saturate=True, capacity=cap)
+    assert cands.size == cap and int(res["n_copied"].sum()) == cap
+    short = 0
+    for o, a in zip(res, ref):
+        got = cands[int(o["cand_offset"]):int(o["cand_offset"] + o["n_copied"])]
+        assert o["n_total"] == a.size and np.array_equal(got, a[:got.size])
+        assert (o["status"] == tb.TB_ERR_OVERFLOW) == (got.size < a.size)
+        short += got.size < a.size
+    assert short >= 1
