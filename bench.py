@@ -119,6 +119,32 @@ def traffic_record(kernel: str, workload_name: str, what: str = "traffic"):
     return rec
 
 
+TRACE_SUMMARY = {"c2": "kernel_trace_c2_n2e23.md", "c2_series_whitening": "kernel_trace_c2_series_whitening_n2e23.md"}
+
+
+def trace_average(kernel: str, workload_name: str):
+    """The kernel's average launch duration in the committed rocprofv3 kernel
+    trace of this workload (microseconds), if that trace was taken on the
+    current kernel source."""
+    name = TRACE_SUMMARY.get(workload_name)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        text = f.read()
+    src = os.path.join(ROOT, "paper_2112_11991_amd", "csrc", "tb_kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() not in text:
+            return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.split("|")]
+        if len(cells) > 4 and cells[1].startswith("`%s<" % kernel):
+            return {"avg_us": float(cells[4]), "calls": int(cells[2]), "file": "profiles/" + name}
+    return None
+
+
 def host_threads():
     """Threads for the CPU oracle: every core this process may use, i.e. its
     CPU affinity, capped by OMP_NUM_THREADS where the host sets it (a GPU
@@ -172,6 +198,13 @@ def kernel_report(plan, n_avg: float, workload_name: str, tile: int, series_whit
     roof = dict(bound="hbm", kernel=d["kernel"], **hbm)
     roof.update({"traffic": None if tr is None else tr["bytes_per_launch"], "avg_launch_ms": d["avg_ms"],
                  "templates_per_launch": tmpl / max(1, d["launches"])})
+    ta = trace_average(d["kernel"], workload_name)
+    if ta is not None:
+        # events bracket each sampled kernel, so their interval also holds its
+        # dispatch after the preceding event; the trace times the kernel alone
+        roof["trace_avg_launch_ms"] = ta["avg_us"] * 1e-3
+        roof["events_over_trace"] = d["avg_ms"] / (ta["avg_us"] * 1e-3)
+        roof["trace_file"] = ta["file"]
     vr = traffic_record(d["kernel"], workload_name, "valu")
     if vr is not None:
         # VALU issue: the counted wave instructions x 64 lanes over the live launch time
