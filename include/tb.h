@@ -263,7 +263,8 @@ tb_status tb_set_budget(tb_plan_t plan, uint64_t budget_bytes);
  * TB_ERR_BUDGET if a request does not fit the budget with nothing running;
  * TB_ERR_INVALID_ARG for bad arguments (checked before anything is queued);
  * otherwise the first error of an underlying call, after the requests in
- * flight have been waited for and released. */
+ * flight have been waited for and released (requests not served keep status
+ * TB_ERR_NOT_READY and times -1; the failing one carries the error). */
 typedef struct {
     double t_arrival_s;
     int32_t series_id;

@@ -157,3 +157,25 @@ def test_serve_realtime_order_and_shared_capacity(tb):
         assert (o["status"] == tb.TB_ERR_OVERFLOW) == (got.size < a.size)
         short += got.size < a.size
     assert short >= 1
+
+
+def test_serve_stops_on_an_error_and_releases(tb):
+    """A request naming an unknown series ends the stream with that error;
+    requests already admitted are waited for and released, and the same plan
+    then serves the valid requests with every result equal to its result
+    alone."""
+    lens, series = _pool()
+    reqs = _trace(n_req=6, seed=507)
+    ref = _alone(tb, series, reqs)
+    with tb.Plan(fmin_hz=2.0, ring_capacity=1 << 16, lanes=2) as plan:
+        sids = [plan.load_series(x, 64e-6) for x in series]
+        rq = [(0.0, sids[s], tm, first) for _, s, tm, first in reqs]
+        bad = list(rq)
+        bad[3] = (0.0, 999, rq[3][2], rq[3][3])
+        with pytest.raises(tb.TbError) as e:
+            plan.serve(bad, saturate=True)
+        assert e.value.status == tb.TB_ERR_UNKNOWN_ID
+        res, cands, _ = plan.serve(rq, saturate=True)
+    assert np.all(res["status"] == tb.TB_OK)
+    for o, a in zip(res, ref):
+        assert np.array_equal(cands[int(o["cand_offset"]):int(o["cand_offset"] + o["n_copied"])], a)
