@@ -64,6 +64,12 @@ CASES = [
     # resident series (8,223 samples at 2^16): the exact per-sample path,
     # though the polynomials would be accurate
     (16, 64e-6, 4096, (100.0, 3.0, 0.5, 0.0, 0.0)),
+    # whitening windows at the ends of their range: one bin per block (every
+    # whitened bin is ln 2), and blocks wider than 4096 bins (32 values per
+    # thread), whole and with a short last block
+    (10, 64e-6, 1, (30.0, 0.01, 0.3, 0.0, 0.0)),
+    (17, 64e-6, 8192, (7200.0, 0.5, 1.0, 0.0, 0.0)),
+    (16, 64e-6, 5000, (3000.0, 0.4, 2.0, 0.05, 0.3)),
 ]
 
 
@@ -201,6 +207,23 @@ def test_band_limits(tb):
                        series_id=int(sid))
     R.check_candidates(cg, co, [oracle.threshold(1 << l, 6.0) for l in range(5)])
     assert len(cg) > 0 and cg["freq_hz"].min() >= 30.0 - 1.0 / (n * ts) and cg["freq_hz"].max() <= 300.0
+
+
+def test_empty_requests(tb):
+    """A request of no templates completes with no candidates on every
+    entry point (queued search, allocation-free search, served stream), and
+    the plan searches normally afterwards."""
+    n, ts = 1 << 14, 64e-6
+    x = _series(n, ts, seed=15, orbit=synth.Orbit(600.0, 0.2, 1.0), pspin=0.011, snr=30.0)
+    none = np.zeros(0, dtype=tb.TEMPLATE_DTYPE)
+    with tb.Plan(whiten_window=1024) as plan:
+        sid = plan.load_series(x, ts)
+        assert plan.search(sid, none).size == 0
+        c, total = plan.search_noalloc(sid, none)
+        assert c.size == 0 and total == 0
+        res, cands, _ = plan.serve([(0.0, sid, none, 0), (0.0, sid, none, 5)], saturate=True)
+        assert cands.size == 0 and np.all(res["n_total"] == 0) and np.all(res["status"] == tb.TB_OK)
+        assert plan.search(sid, [(600.0, 0.2, 1.0, 0.0, 0.0)]).size > 0
 
 
 def test_batching_invariance(tb):
