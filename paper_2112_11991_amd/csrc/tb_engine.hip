@@ -10,7 +10,6 @@
 #include <memory>
 #include <mutex>
 #include <new>
-#include <thread>
 #include <vector>
 
 #include "tb_internal.h"
@@ -91,36 +90,6 @@ double fold_threshold(int h, double sigma)
         x = nx;
     }
     return x;
-}
-
-const double kSigmaFloor = log_gauss_sf(-30.0);
-
-// Gaussian-equivalent significance of a fold power: z with log_gauss_sf(z) =
-// log Q(h, s).  log_gauss_sf is concave and decreasing, so after the first
-// Newton step every step approaches the root from above; the start is the
-// tail expansion log Q(z) ~ -z^2/2 - log z - log sqrt(2 pi), refined twice.
-double fold_sigma(int h, double s)
-{
-    const double target = log_q(h, s);
-    if (target >= kSigmaFloor) return -30.0;
-    double z = std::sqrt(std::max(0.0, -2.0 * target));
-    if (z > 2.0)
-        for (int i = 0; i < 2; ++i) z = std::sqrt(std::max(0.0, -2.0 * (target + kHalfLog2Pi + std::log(z))));
-    double lo = -30.0, hi = HUGE_VAL;
-    for (int it = 0; it < 100; ++it) {
-        const double lz = log_gauss_sf(z);
-        const double g = lz - target;
-        if (g > 0)
-            lo = z;
-        else
-            hi = z;
-        const double dg = -std::exp(-0.5 * z * z - kHalfLog2Pi - lz);
-        double nz = z - g / dg;
-        if (!(nz > lo && nz < hi)) nz = hi < HUGE_VAL ? 0.5 * (lo + hi) : z + std::max(1.0, std::fabs(z));
-        if (std::fabs(nz - z) < 1e-12 * std::max(1.0, std::fabs(z))) return nz;
-        z = nz;
-    }
-    return z;
 }
 
 // ---------------------------------------------------------------------------
@@ -611,21 +580,19 @@ hipError_t sync_lanes(tb_plan_t p)
     return e;
 }
 
-// A ring record {template, bin, series << 8 | log2 h, S} as a candidate with
-// its significance and fundamental frequency k / (h T).
-void to_candidate(const uint4& q, double T, tb_candidate& c)
+// A ring record after launch_significance, {template, bin | log2 h << 28,
+// sigma, S}, as the candidate of series sid with its fundamental frequency
+// k / (h T).
+void to_candidate(const uint4& q, uint32_t sid, double T, tb_candidate& c)
 {
     std::memset(&c, 0, sizeof(c));
+    c.series_id = sid;
     c.template_id = q.x;
-    c.bin = q.y;
-    c.series_id = q.z >> 8;
-    c.log2_harm = (uint8_t)(q.z & 0xff);
-    float pw;
-    std::memcpy(&pw, &q.w, sizeof(pw));
-    c.power = pw;
-    const int h = 1 << c.log2_harm;
-    c.sigma = (float)fold_sigma(h, (double)pw);
-    c.freq_hz = (double)c.bin / ((double)h * T);
+    c.bin = q.y & 0x0fffffffu;
+    c.log2_harm = (uint8_t)(q.y >> 28);
+    std::memcpy(&c.sigma, &q.z, sizeof(float));
+    std::memcpy(&c.power, &q.w, sizeof(float));
+    c.freq_hz = (double)c.bin / ((double)(1 << c.log2_harm) * T);
 }
 
 void sort_candidates(tb_candidate* c, size_t n)
@@ -638,49 +605,14 @@ void sort_candidates(tb_candidate* c, size_t n)
     });
 }
 
-// Ring records in candidate order (series, template, fold, bin).
+// One request's records (one series) in candidate order: template, fold, bin.
 void sort_records(std::vector<uint4>& raw)
 {
     std::sort(raw.begin(), raw.end(), [](const uint4& a, const uint4& b) {
-        if ((a.z >> 8) != (b.z >> 8)) return (a.z >> 8) < (b.z >> 8);
         if (a.x != b.x) return a.x < b.x;
-        if ((a.z & 0xffu) != (b.z & 0xffu)) return (a.z & 0xffu) < (b.z & 0xffu);
-        return a.y < b.y;
+        if ((a.y >> 28) != (b.y >> 28)) return (a.y >> 28) < (b.y >> 28);
+        return (a.y & 0x0fffffffu) < (b.y & 0x0fffffffu);
     });
-}
-
-// Records to candidates, in order; long lists are split over up to 16 host
-// threads (about a third of a microsecond per significance).
-void to_candidates(const uint4* raw, size_t n, double T, tb_candidate* out)
-{
-    constexpr size_t kPerThread = 1024;
-    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-    const size_t nt = std::min<size_t>({hw, (size_t)16, (n + kPerThread - 1) / kPerThread});
-    auto run = [=](size_t a, size_t b) {
-        for (size_t i = a; i < b; ++i) to_candidate(raw[i], T, out[i]);
-    };
-    std::vector<std::thread> pool;
-    size_t done = 0;
-    if (nt > 1) {
-        const size_t per = (n + nt - 1) / nt;
-        try {
-            for (size_t t = 1; t < nt; ++t) {
-                const size_t a = t * per, b = std::min(n, a + per);
-                if (a < b) pool.emplace_back(run, a, b);
-            }
-            done = pool.empty() ? 0 : per;
-        } catch (...) {
-            for (auto& th : pool) th.join();
-            pool.clear();
-            done = 0;
-        }
-    }
-    if (pool.empty()) {
-        run(0, n);
-        return;
-    }
-    run(0, done);
-    for (auto& th : pool) th.join();
 }
 
 tb_status fetch(tb_plan_t p, Req& r)
@@ -700,7 +632,7 @@ tb_status fetch(tb_plan_t p, Req& r)
     const double T = (double)r.n * r.tsamp;
     sort_records(raw);
     r.cands.resize((size_t)keep);
-    to_candidates(raw.data(), raw.size(), T, r.cands.data());
+    for (size_t i = 0; i < raw.size(); ++i) to_candidate(raw[i], (uint32_t)r.series, T, r.cands[i]);
     r.total = total;
     r.fetched = true;
     return TB_OK;
@@ -1354,7 +1286,8 @@ tb_status tb_search_templates(tb_plan_t p, int32_t sid, const tb_template* t, ui
         if (hipEventRecord(done, crew.streams[c]) != hipSuccess || hipStreamWaitEvent(stream, done, 0) != hipSuccess)
             return fail(TB_ERR_DEVICE);
     }
-    if (hipEventRecord(r.ev1, stream) != hipSuccess) return fail(TB_ERR_DEVICE);
+    if (launch_significance(ring, counter, r.cap, stream) != hipSuccess || hipEventRecord(r.ev1, stream) != hipSuccess)
+        return fail(TB_ERR_DEVICE);
     // pending work split by waves taken
     {
         const size_t nc = crew.streams.size(), nw = (count + (uint32_t)ws->B - 1) / (uint32_t)ws->B;
@@ -1420,6 +1353,7 @@ tb_status tb_search_templates_noalloc(tb_plan_t p, int32_t sid, const tb_templat
                         none, s, nullptr);
         w0 += (uint32_t)nslots;
     }
+    if (e == hipSuccess) e = launch_significance(ring, counter, capacity, s);
     uint32_t total = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&total, counter, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1436,7 +1370,7 @@ tb_status tb_search_templates_noalloc(tb_plan_t p, int32_t sid, const tb_templat
         uint4 q;
         std::memcpy(&q, (const char*)out + i * sizeof(uint4), sizeof(q));
         tb_candidate c;
-        to_candidate(q, T, c);
+        to_candidate(q, (uint32_t)sid, T, c);
         std::memcpy(&out[i], &c, sizeof(c));
     }
     sort_candidates(out, (size_t)keep);

@@ -161,6 +161,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s)
 // Rewrites a mean-removed series into the tile order pass 1 reads.
 hipError_t launch_tile_series(const Geometry& g, const float* in, float* out, hipStream_t s);
 int harmsum_tile();
+// Rewrites the first min(*counter, cap) candidate records in place with their
+// significance: {template, bin | log2 h << 28, sigma bits, S} (tb_readback.hip).
+hipError_t launch_significance(uint4* ring, const uint32_t* counter, uint64_t cap, hipStream_t s);
 // Candidate records a request's device ring holds (the plan's ring_capacity).
 uint64_t plan_ring_capacity(tb_plan_t p);
 // Dedispersion: integer delays delay[c * ldd + d] (ldd = ndm rounded up to the
