@@ -302,7 +302,10 @@ tb_status get_geometry(tb_plan_t p, int log2n, Geometry** out)
     // rows of 2R samples: enough for a delay swing of n/8 samples, at most
     // 2^PAD_REACH_LOG2, plus two for rounding
     g.P = (int)(std::min<int64_t>(g.n / 8, (int64_t)1 << PAD_REACH_LOG2) / (2 * g.R)) + 2;
-    g.D2 = (int)(TE / g.R);
+    // pass-2 workgroups take at most 8192 points (16 columns of 512 at 2^24):
+    // with one column per pass-1 workgroup any column count divides the
+    // exchange evenly, and the 8192-point shape runs two workgroups per CU
+    g.D2 = (int)((TE > 8192 && g.C1 == 1 ? 8192 : TE) / g.R);
     g.W = (int)p->cfg.whiten_window;
     g.nblk = (int)((g.M + g.W - 1) / g.W);
     g.htile = harmsum_tile();
