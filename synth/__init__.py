@@ -177,6 +177,18 @@ def c3_elliptical(n_templates: int = 50000, n: int = 1 << 24) -> Workload:
     return Workload("c3_elliptical_2^24", ts, [x.astype(np.float32)], tm, [(0, orb, 0.030)])
 
 
+def table3_series(n: int = 1 << 24) -> Workload:
+    """The series of the paper's circular-search timing (Tables 2 and 3): one
+    series of 2^24 samples at 256 us (71.6 min), noise plus a 30 ms pulsar (5%
+    duty, S/N 15) in a circular orbit P_orb = 8 h, tau = 10 lt-s, alpha = 1.0.
+    The bank (the Table 1 circular random bank) is drawn by the caller."""
+    rn, _, _, _, _, _ = streams(7)
+    ts = 256e-6
+    orb = Orbit(8.0 * HOUR, 10.0, 1.0)
+    x = inject(white_noise(n, rn), pulse_train(n, ts, 0.030, 0.05, orb), 15.0)
+    return Workload("t3_circular_2^24", ts, [x.astype(np.float32)], None, [(0, orb, 0.030)])
+
+
 def c4_batched(n_series: int = 32, n_templates: int = 4096, log2_lengths=(20, 21, 22, 23)) -> Workload:
     """32 series (DM trials) of lengths drawn from 2^20..2^23 at 64 us, 4 of
     them with circular binaries (P_spin 20-40 ms, S/N 15); 4096 shared circular
