@@ -944,9 +944,16 @@ __device__ __forceinline__ float block_median(const uint32_t (&v)[VPT], int cnt,
         const int nbin = pass == 0 ? MED_BINS : 1024;
         const uint32_t dmask = (uint32_t)nbin - 1;
         const int per = nbin / NT;  // bins per thread: 8, then 4
+        if (pass == 0 && cnt == VPT * NT) {
+            // a whole block: every value counts in the first digit, with no
+            // per-value predicate
 #pragma unroll
-        for (int i = 0; i < VPT; ++i)
-            if ((v[i] & mask) == prefix) atomicAdd(&hist[(v[i] >> shift) & dmask], 1u);
+            for (int i = 0; i < VPT; ++i) atomicAdd(&hist[(v[i] >> shift) & dmask], 1u);
+        } else {
+#pragma unroll
+            for (int i = 0; i < VPT; ++i)
+                if ((v[i] & mask) == prefix) atomicAdd(&hist[(v[i] >> shift) & dmask], 1u);
+        }
         __syncthreads();
         uint32_t cnts[8];
         uint32_t tot = 0;
@@ -999,6 +1006,12 @@ __device__ __forceinline__ int load_block(const float* __restrict__ Ps, int64_t 
 {
     const int64_t start = 1 + (int64_t)b * W;
     const int cnt = (int)((M - (int64_t)b * W) < W ? (M - (int64_t)b * W) : W);
+    if (cnt == VPT * NT) {
+        const float* row = Ps + start + threadIdx.x;
+#pragma unroll
+        for (int i = 0; i < VPT; ++i) v[i] = __float_as_uint(row[i * NT]);
+        return cnt;
+    }
 #pragma unroll
     for (int i = 0; i < VPT; ++i) {
         const int q = (int)threadIdx.x + i * NT;
@@ -1143,6 +1156,16 @@ __global__ __launch_bounds__(NT) void k_median_whiten(const float* __restrict__ 
         if (threadIdx.x == 0) md[b] = m_c;
         const WhitenLine L = whiten_line_of(b, (int)M, W, nblk, m_l, m_c, m_r);
         int r = nzap ? first_zap(zap, nzap, L.start) : 0;
+        if (cnt == VPT * NT && !nzap) {
+            float* qrow = Qs + L.start + threadIdx.x;
+#pragma unroll
+            for (int i = 0; i < VPT; ++i) {
+                const int q = L.start + (int)threadIdx.x + i * NT;
+                const float level = L.level(q);
+                const float p = __uint_as_float(cur[i]);
+                qrow[i * NT] = level > 0.0f ? p * (LN2F * __builtin_amdgcn_rcpf(level)) : 0.0f;
+            }
+        } else
 #pragma unroll
         for (int i = 0; i < VPT; ++i) {
             const int qi = (int)threadIdx.x + i * NT;
