@@ -188,3 +188,49 @@ def test_uneven_length_batch_on_lanes(tb):
         _say("  series %d (2^%d): matched %d, near-threshold %d" % (i, x.size.bit_length() - 1, matched, exempt))
         assert matched > 0
         _same_best(cg, co)
+
+
+def test_uneven_length_search_at_full_size_sampled(tb):
+    """The batched uneven-length workload at its full size and in the
+    benchmark's launch configuration (32 series of 2^20 .. 2^23 samples, 4096
+    shared circular templates, one request per series on four lanes, the
+    library's default waves): the candidates of eight sampled (series,
+    template) pairs, the series carrying binaries and their true orbits among
+    them, against the oracle one template at a time (three of the sampled
+    bank templates fall on the series with binaries, where the pulsar shows
+    in most templates)."""
+    w = synth.c4_batched()
+    ts, sigma = w.tsamp, w.sigma
+    tms = np.concatenate([w.templates] + [orb.as_template() for _, orb, _ in w.truths])
+    _say("uneven-length full size: %d series x %d templates on 4 lanes" % (len(w.series), len(tms)))
+    with tb.Plan(lanes=4, threshold_sigma=sigma, fmin_hz=w.fmin_hz, ring_capacity=1 << 18) as plan:
+        sids = [plan.load_series(x, ts) for x in w.series]
+        rids = [plan.submit(sid, tms) for sid in sids]
+        got = []
+        for rid in rids:
+            got.append(plan.candidates(rid)[0])
+            plan.release(rid)
+    rng = np.random.default_rng(77)
+    nb = len(w.templates)
+    carriers = [i for i, _, _ in w.truths]
+    pairs = [(i, nb + k) for k, i in enumerate(carriers)]
+    # bank templates on the series with binaries (the pulsar shows in most of
+    # them) and one on any series
+    pairs += [(carriers[k % len(carriers)], int(rng.integers(nb))) for k in range(3)]
+    pairs += [(int(rng.integers(len(w.series))), int(rng.integers(nb)))]
+    thr = [oracle.threshold(1 << l, sigma) for l in range(5)]
+    bank_hits = 0
+    for s, t in pairs:
+        x = w.series[s]
+        co = oracle.search(oracle.mean_subtract(x), oracle.config(x.size, ts, threshold_sigma=sigma,
+                                                                   fmin_hz=w.fmin_hz),
+                           tms[t:t + 1], first_template_id=t, series_id=int(sids[s]))
+        cg = got[s][got[s]["template_id"] == t]
+        matched, exempt = R.check_candidates(cg, co, thr)
+        _say("  series %d (2^%d) template %d: %d candidates, near-threshold %d" % (
+            s, x.size.bit_length() - 1, t, matched, exempt))
+        if t >= nb:
+            assert matched > 0
+        else:
+            bank_hits += matched
+    assert bank_hits > 0
