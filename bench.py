@@ -114,7 +114,7 @@ def wave_shape(n: int, batch: int = 0):
     """Templates per wave B and per pass-1/2 launch BY the library uses for
     series of n samples (mirrors its defaults)."""
     M = n // 2
-    B = batch or min(256, max(4, (1 << 27) // M))
+    B = batch or min(256, max(4, (1 << 28) // M))
     return B, max(1, min(B, (1 << 24) // M))
 
 

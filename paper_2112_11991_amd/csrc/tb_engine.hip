@@ -351,7 +351,7 @@ int default_batch(const tb_plan_t p, int64_t M)
     auto sh = p->shape.find(ilog2((uint64_t)M) + 1);
     if (sh != p->shape.end() && sh->second.second) return sh->second.second;
     if (p->cfg.batch_templates) return (int)p->cfg.batch_templates;
-    int64_t b = ((int64_t)1 << 27) / M;  // 2^27 bins in flight: 32 templates at 2^23 samples
+    int64_t b = ((int64_t)1 << 28) / M;  // 2^28 bins in flight: 64 templates at 2^23 samples
     return (int)std::min<int64_t>(256, std::max<int64_t>(4, b));
 }
 

@@ -1534,10 +1534,10 @@ hipError_t launch_wave(const Geometry& g, const float* x, double tsamp, const Tm
         // the profile then has no launches of its own)
         if ((e = mark(marks, K_MEDIAN, s)) != hipSuccess) return e;
         // as many blocks per workgroup as keep about 1024 workgroups (four per
-        // compute unit, one round at this kernel's occupancy), at most 32: each
+        // compute unit, one round at this kernel's occupancy), at most 64: each
         // workgroup recomputes the medians of the two blocks just outside its
         // run, so longer runs re-read less of the spectrum
-        const int mw = std::max(2, std::min(32, g.nblk * nslots / 1024));
+        const int mw = std::max(2, std::min(64, g.nblk * nslots / 1024));
         const dim3 grid((g.nblk + mw - 1) / mw, nslots);
         if (g.W <= 16 * NT)
             hipLaunchKernelGGL((k_median_whiten<16>), grid, dim3(NT), 0, s, ws.P, ws.Q, ws.p_stride, g.M, g.W,

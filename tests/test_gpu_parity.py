@@ -319,18 +319,18 @@ def test_device_resident_input(tb):
 
 def test_full_size_circular_survey(tb):
     """2^23 samples with red noise and a pulsar, in the benchmark's launch
-    configuration (the library defaults: 32 templates per wave, passes 1-2 in
-    groups of 4, 8192-point tiles, 32 median blocks per workgroup): bit-exact
+    configuration (the library defaults: 64 templates per wave, passes 1-2 in
+    groups of 4, 8192-point tiles, 64 median blocks per workgroup): bit-exact
     indices and whole-spectrum power parity for one template, candidate
-    parity for all 32 templates of the wave (31 of the bank and the injected
+    parity for all 64 templates of the wave (63 of the bank and the injected
     orbit)."""
-    w = synth.c2_survey(n_templates=31)
+    w = synth.c2_survey(n_templates=63)
     w.templates = np.concatenate([w.templates, w.truths[0][1].as_template()])
     x, ts = w.series[0], w.tsamp
     n = x.size
     cfg = oracle.config(n, ts)
     x0 = oracle.mean_subtract(x)
-    _say("full size: 2^23, 32 templates")
+    _say("full size: 2^23, 64 templates")
     with tb.Plan() as plan:
         sid = plan.load_series(x, ts)
         cg = plan.search(sid, w.templates)
