@@ -65,7 +65,8 @@ typedef struct {
     uint32_t max_log2n;        /* largest series accepted, log2 samples, 10..24 */
     uint32_t harm_max;         /* harmonics summed: 1, 2, 4, 8 or 16 (Sec. 2.1; 16 in Sec. 5.2) */
     uint32_t whiten_window;    /* W, spectral bins per median block of the whitening, 1..8192 */
-    uint32_t batch_templates;  /* templates in flight per launch; 0 = chosen by the plan */
+    uint32_t batch_templates;  /* templates in flight per wave; 0 = the plan's choice, 2^28 / (n/2)
+                                  clamped to 4..256 (64 at n = 2^23) */
     double threshold_sigma;    /* one-sided Gaussian-equivalent false-alarm threshold (Sec. 2.1) */
     double fmin_hz;            /* lowest fundamental searched (default 1 Hz) */
     double fmax_hz;            /* highest fundamental searched; 0 = Nyquist */
