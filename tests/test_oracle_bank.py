@@ -272,5 +272,7 @@ def test_planted_bank_mistakes_are_caught(oracle_lib, name):
     assert src.count(old) == 1, name
     mod = types.ModuleType("bank_mutant")
     exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
-    errs = _bank_errors(mod)
-    assert any(rp >= 1e-25 or rf > 1.0 for rp, rf in errs), name
+    with np.errstate(invalid="ignore"):  # a slip may leave the metric indefinite (det of NaN)
+        errs = _bank_errors(mod)
+    # caught: some case leaves the tolerance, NaN included
+    assert any(not (rp < 1e-25 and rf <= 1.0) for rp, rf in errs), name
