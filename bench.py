@@ -456,6 +456,15 @@ def run_bank(args, tb, torch):
     ms_step = 1e3 * dt / args.steps
     log("timed %d steps: %.1f ms/step, %.0f templates/s, %d candidates/step" % (args.steps, ms_step, value,
                                                                                 ncand // max(1, args.steps)))
+    # The series are resident when the timed region starts.  The host hand-over
+    # is timed apart: every series loaded once more from pageable host memory
+    # (copy to HBM and its preprocessing on the device), then unloaded.
+    t1 = time.perf_counter()
+    extra = [plan.load_series(s, w.tsamp, flags=load_flags) for s in w.series]
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t1
+    for sid in extra:
+        plan.unload_series(sid)
     samples_total = float(sum(s.size for s in w.series))
     metric = METRIC if args.workload == "c2" else "templates/s (%s)" % args.workload
     if args.workload == "t3":
@@ -469,6 +478,10 @@ def run_bank(args, tb, torch):
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": conf, "candidates_per_step": ncand // max(1, args.steps),
            "algorithmic_gbs": 12.0 * samples_total * ntemp * args.steps / dt / 1e9}
+    out["pcie_inclusive"] = {
+        "value": nitems / (dt / args.steps + load_s), "unit": "templates/s", "series_load_ms": 1e3 * load_s,
+        "series_bytes": int(sum(s.nbytes for s in w.series)),
+        "basis": "one step plus one load of every series from pageable host memory (not the headline value)"}
     out["algorithmic_hbm_frac"] = out["algorithmic_gbs"] / PEAK_HBM_GBS
     # whole path: 12n bytes per template plus the series read of every pass-1 launch
     batch = args.batch or 0
