@@ -594,7 +594,7 @@ def served(tb, torch, nreq, lanes=4, with_plain=True):
 
 
 def batching_report(tb, lengths=(20, 21, 22, 23), ntemp=256, tsamp=64e-6, reps=2):
-    """Batched search (the library's waves of 16-128 templates, four lanes)
+    """Batched search (the library's waves of 64-256 templates, four lanes)
     against the one-template-per-launch path (every kernel launched for a
     single template, one stream) on the same noise series and the same 256
     circular templates, for each series length of the uneven-length search."""
