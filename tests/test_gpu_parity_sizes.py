@@ -2,9 +2,10 @@
 the default pass-2 shapes of 2^20 and 2^22 samples (8192-point tiles, 64- and
 256-point pass-2 transforms), the elliptical configuration at its full size
 (2^24 samples at 256 us, BT delay with a Newton solve of Kepler's equation,
-App. A.1 and Alg. 1) with the widest orbit of its prior, and a batch shaped
+App. A.1 and Alg. 1) with the widest orbit of its prior, a batch shaped
 like the uneven-length search (four series of 2^20 .. 2^23 samples searched at
-once on four lanes)."""
+once on four lanes), and the paper's circular timing configuration with the
+extremes of its Table 1 prior."""
 import math
 import sys
 
@@ -151,6 +152,49 @@ def test_elliptical_full_size_bt_newton(tb, c3, tile):
     assert matched > 0
     _same_best(cg, co)
     assert cg[np.argmax(cg["sigma"])]["template_id"] == 1  # the injected orbit
+
+
+@pytest.fixture(scope="module")
+def t3():
+    return synth.table3_series()
+
+
+def _kepler_tau(porb_s, m_p=1.4, m_c=8.0):
+    """Largest projected semi-major axis (lt-s) the Table 1 prior allows at
+    P_orb: Kepler's third law with the lightest pulsar and the heaviest
+    companion (Sec. 3.1)."""
+    from oracle.bank import T_SUN
+
+    return T_SUN ** (1 / 3) * (2 * math.pi / porb_s) ** (-2 / 3) * m_c / (m_p + m_c) ** (2 / 3)
+
+
+def test_table1_prior_extremes_full_size(tb, t3):
+    """The paper's circular timing configuration (2^24 samples at 256 us, the
+    Table 1 prior: P_orb 6-12 h, tau up to the Kepler limit) in the plan's
+    default launch shape: bit-exact indices and whole-spectrum parity for the
+    orbit whose delay changes fastest (6 h at its Kepler limit, about 7 lt-s),
+    candidate parity for it, the 12 h orbit at its limit and the injected
+    orbit."""
+    x, ts = t3.series[0], t3.tsamp
+    n = x.size
+    fast = (6.0 * HOUR, 0.999 * _kepler_tau(6.0 * HOUR), 2.0, 0.0, 0.0)
+    wide = (12.0 * HOUR, 0.999 * _kepler_tau(12.0 * HOUR), 4.0, 0.0, 0.0)
+    assert 6.9 < fast[1] < 7.0 and 11.0 < wide[1] < 11.1
+    assert chunk_points(fast, n, ts, 16384) == 16 and chunk_points(wide, n, ts, 16384) == 16
+    tms = np.concatenate([np.array([fast, wide], dtype=synth.TEMPLATE_DTYPE), t3.truths[0][1].as_template()])
+    _say("table 1 extremes at 2^24: tau %.3f at 6 h, %.3f at 12 h" % (fast[1], wide[1]))
+    x0 = oracle.mean_subtract(x)
+    cfg = oracle.config(n, ts)
+    with tb.Plan() as plan:
+        sid = plan.load_series(x, ts)
+        cg = plan.search(sid, tms)
+        ex = _stage_check(plan, sid, x0, cfg, fast, 4096)
+    co = oracle.search(x0, cfg, tms, series_id=int(sid))
+    matched, exempt = R.check_candidates(cg, co, [oracle.threshold(1 << l, 6.0) for l in range(5)])
+    _say("  tie-exempt %d; candidates matched %d, near-threshold %d" % (ex, matched, exempt))
+    assert matched > 0
+    _same_best(cg, co)
+    assert cg[np.argmax(cg["sigma"])]["template_id"] == 2  # the injected orbit
 
 
 def test_uneven_length_batch_on_lanes(tb):
