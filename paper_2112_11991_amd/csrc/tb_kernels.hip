@@ -723,6 +723,10 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
         };
         const uint32_t SP = (uint32_t)(S + P);
         float v[32];
+        // The gather's waves issue at raised priority, so that a CU's other
+        // workgroup, busy with its transform, yields issue slots until these
+        // loads are in flight.
+        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             int jp, ip0, ip1;
@@ -730,6 +734,7 @@ __global__ __launch_bounds__(C1 * S / 16, 4) void k_fft1(const float* __restrict
             v[2 * i] = load_sample<C1>(x, ip0, lgR, SP);
             v[2 * i + 1] = load_sample<C1>(x, ip1, lgR, SP);
         }
+        __builtin_amdgcn_s_setprio(0);
         if (src_out) {
             for (int i = 0; i < 16; ++i) {
                 int jp, ip0, ip1;
